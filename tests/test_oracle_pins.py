@@ -1,0 +1,272 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+Each test names what it pins.  None of them re-types an oracle formula: they
+compare against an independent route (brute-force Fock space, spin-orbital
+algebra, a textbook special case, a closed form or an identity).
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from synth import gen
+from oracle import dense, fockspace, folded, pencil, spinorb
+
+
+# ---------------------------------------------------------------------------
+# P6: brute-force Fock space vs the spin-orbital closed forms
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("no,nv,seed", [(2, 3, 1), (3, 3, 2), (2, 4, 3), (2, 2, 4)])
+def test_p6_spinorbital_forms_equal_defining_expectation_values(no, nv, seed):
+    """S2, A2 (symmetrized, W-cross terms included), B2 and first order vs brute force."""
+    eps, _, V = spinorb.spinless_system(seed, no, nv)
+    r = fockspace.MP2Response(eps, no, V)
+    S0, S2 = r.metric()
+    A0, A1, A2 = r.a_block()
+    B0, B1, B2 = r.b_block()
+    Ac = [spinorb.assemble(eps, no, V, k) for k in (0, 1, 2)]
+    scale = max(np.abs(A2).max(), np.abs(B2).max(), np.abs(S2).max())
+    assert scale > 1e-5                     # the second-order pieces are not trivially zero
+    np.testing.assert_allclose(S0, Ac[0][2], atol=1e-14)
+    np.testing.assert_allclose(A0, Ac[0][0], atol=1e-14)
+    np.testing.assert_allclose(A0 + A1, Ac[1][0], atol=1e-14)
+    np.testing.assert_allclose(B1, Ac[1][1], atol=1e-14)
+    np.testing.assert_allclose(B0, 0, atol=1e-15)
+    np.testing.assert_allclose(S2, Ac[2][2] - Ac[1][2], atol=1e-14)
+    np.testing.assert_allclose(A2, Ac[2][0] - Ac[1][0], atol=1e-14)
+    np.testing.assert_allclose(B2, Ac[2][1] - Ac[1][1], atol=1e-14)
+
+
+def test_p6_first_order_is_tdhf_and_fock_is_diagonal():
+    """First order equals textbook TDHF: A1 = <aj||ib>, B1 = <ab||ij>; Brillouin holds."""
+    eps, no, V = spinorb.spinless_system(11, 2, 3)
+    r = fockspace.MP2Response(eps, no, V)
+    assert r.brillouin_max() < 1e-14
+    _, A1, _ = r.a_block()
+    _, B1, _ = r.b_block()
+    nv = len(eps) - no
+    for i in range(no):
+        for a in range(nv):
+            for j in range(no):
+                for b in range(nv):
+                    assert abs(A1[i * nv + a, j * nv + b] - V[no + a, j, i, no + b]) < 1e-14
+                    assert abs(B1[i * nv + a, j * nv + b] - V[no + a, no + b, i, j]) < 1e-14
+
+
+def test_p6_literal_reading_differs_from_r2():
+    """The H0-only (literal) second-order A is 1/2(Delta_ai + Delta_bj) S2; the W-cross part is not zero."""
+    eps, no, V = spinorb.spinless_system(5, 2, 3)
+    r = fockspace.MP2Response(eps, no, V)
+    h0_part, w_part = r.a2_parts()
+    _, S2 = r.metric()
+    nv = len(eps) - no
+    delta = (eps[no:][None, :] - eps[:no][:, None]).reshape(-1)
+    np.testing.assert_allclose(h0_part, 0.5 * (delta[:, None] + delta[None, :]) * S2, atol=1e-14)
+    assert np.abs(w_part).max() > 1e-4
+
+
+@pytest.mark.parametrize("no,nv,seed", [(2, 3, 1), (3, 2, 4)])
+def test_p10_mp2_energy_brute_force(no, nv, seed):
+    """<0|W_N R0 W_N|0> from explicit matrices equals 1/4 sum t <ij||ab> (textbook MP2)."""
+    eps, _, V = spinorb.spinless_system(seed, no, nv)
+    r = fockspace.MP2Response(eps, no, V)
+    assert abs(r.mp2_energy() - spinorb.mp2_energy(eps, no, V)) < 1e-15
+    # Psi1 has only doubly excited components
+    for k, d in enumerate(r.fs.dets):
+        holes = bin(((1 << no) - 1) & ~d).count("1")
+        if abs(r.psi1[k]) > 1e-14:
+            assert holes == 2
+
+
+# ---------------------------------------------------------------------------
+# P7: spin adaptation (spatial closed-shell singlet vs spin orbitals)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("o,v,naux,seed", [(2, 3, 5, 1), (3, 4, 7, 2), (1, 2, 3, 3)])
+def test_p7_singlet_projection_equals_spin_adapted(o, v, naux, seed):
+    sys = gen(seed, o, v, naux, b_scale=0.6)
+    eps_so, no_so, V = spinorb.spinorbital_system(sys)
+    for order in (1, 2):
+        Aso, Bso, Sso = spinorb.assemble(eps_so, no_so, V, order)
+        A, B, S = dense.assemble(sys, order)
+        for Mso, M in ((Aso, A), (Bso, B), (Sso, S)):
+            sing, _ = spinorb.singlet_triplet_projection(Mso, o, v)
+            np.testing.assert_allclose(sing, M, atol=1e-14)
+    assert abs(dense.mp2_energy(sys) - spinorb.mp2_energy(eps_so, no_so, V)) < 1e-14
+
+
+def test_p7_brute_force_closed_shell_singlet():
+    """Closed-shell system through the Fock-space route directly, singlet-projected."""
+    o, v = 2, 3
+    sys = gen(9, o, v, 4, b_scale=0.6)
+    eps_so, no_so, V = spinorb.spinorbital_system(sys)
+    r = fockspace.MP2Response(eps_so, no_so, V)
+    S0, S2 = r.metric()
+    A0, A1, A2 = r.a_block()
+    _, B1, B2 = r.b_block()
+    A, B, S = dense.assemble(sys, 2)
+    np.testing.assert_allclose(spinorb.singlet_triplet_projection(A0 + A1 + A2, o, v)[0], A, atol=1e-14)
+    np.testing.assert_allclose(spinorb.singlet_triplet_projection(B1 + B2, o, v)[0], B, atol=1e-14)
+    np.testing.assert_allclose(spinorb.singlet_triplet_projection(S0 + S2, o, v)[0], S, atol=1e-14)
+
+
+def test_p4_two_level_closed_form_against_brute_force():
+    """o = v = 1: omega = sqrt(A^2 - B^2)/S with the scalar second-order A, B, S.
+
+    The scalars are the singlet projection of the brute-force Fock-space
+    matrices (4 spin orbitals, 2 electrons); the pencil solver must return the
+    closed-form root.
+    """
+    sys = gen(21, 1, 1, 3, b_scale=0.8)
+    eps_so, no_so, V = spinorb.spinorbital_system(sys)
+    r = fockspace.MP2Response(eps_so, no_so, V)
+    S0, S2 = r.metric()
+    A0, A1, A2 = r.a_block()
+    _, B1, B2 = r.b_block()
+    a = spinorb.singlet_triplet_projection(A0 + A1 + A2, 1, 1)[0][0, 0]
+    b = spinorb.singlet_triplet_projection(B1 + B2, 1, 1)[0][0, 0]
+    s = spinorb.singlet_triplet_projection(S0 + S2, 1, 1)[0][0, 0]
+    w_closed = np.sqrt(a * a - b * b) / s
+    A, B, S = dense.assemble(sys, 2)
+    w, X, Y = pencil.solve_all(A, B, S)
+    assert abs(w[0] - w_closed) < 1e-14
+    # first order: omega = sqrt((A - B)(A + B))
+    a1 = spinorb.singlet_triplet_projection(A0 + A1, 1, 1)[0][0, 0]
+    b1 = spinorb.singlet_triplet_projection(B1, 1, 1)[0][0, 0]
+    w1, _, _ = pencil.solve_all(*dense.assemble(sys, 1))
+    assert abs(w1[0] - np.sqrt((a1 - b1) * (a1 + b1))) < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# P1, P2, P3, P5: special cases and structure
+# ---------------------------------------------------------------------------
+def test_p1_zero_integrals_give_orbital_energy_differences():
+    sys = gen(1, 8, 24, 64).scaled(0.0)
+    for order in (0, 1, 2):
+        A, B, S = dense.assemble(sys, order)
+        w, X, Y = pencil.solve_all(A, B, S)
+        delta = np.sort((sys.eps_v[None, :] - sys.eps_o[:, None]).reshape(-1))
+        assert np.array_equal(w, np.sqrt(delta * delta)) or np.abs(w - delta).max() < 1e-15
+        e, Xw, Yw, f = pencil.window_solve(A, B, S, sys.dip, 0.5, 6)
+        d = (sys.eps_v[None, :] - sys.eps_o[:, None]).reshape(-1)
+        pick = np.sort(np.argsort(np.abs(d - 0.5), kind="stable")[:6])
+        pick = pick[np.argsort(d[pick])]
+        np.testing.assert_allclose(e, d[pick], rtol=0, atol=1e-15)
+        mu2 = np.sum(sys.dip.reshape(3, -1) ** 2, axis=0)
+        np.testing.assert_allclose(f, (4.0 / 3.0) * d[pick] * mu2[pick], rtol=1e-13)
+
+
+def test_p2_symmetry_and_first_order_metric():
+    sys = gen(1, 8, 24, 64)
+    for order in (1, 2):
+        A, B, S = dense.assemble(sys, order)
+        for M in (A, B, S):
+            assert np.abs(M - M.T).max() <= 1e-14 * np.abs(M).max()
+        if order == 1:
+            assert np.array_equal(S, np.eye(len(S)))
+        assert np.linalg.eigvalsh(S).min() > 0
+        assert np.linalg.eigvalsh(A - B).min() > 0 and np.linalg.eigvalsh(A + B).min() > 0
+
+
+def test_p3_plus_minus_pairs_general_eig():
+    sys = gen(1, 8, 24, 64)
+    for order in (1, 2):
+        M, Sig = dense.build_M(sys, order)
+        w, imax = pencil.pencil_eigvals_general(M, Sig)
+        assert imax < 1e-12
+        np.testing.assert_allclose(np.sort(w), np.sort(-w), atol=1e-12)
+        om, _, _ = pencil.solve_all(*dense.assemble(sys, order))
+        np.testing.assert_allclose(np.sort(np.concatenate([om, -om])), w, atol=1e-12)
+
+
+def test_p5_tda_limit_is_generalized_symmetric_eig():
+    sys = gen(3, 6, 20, 40, b_scale=0.3)
+    A, B, S = dense.assemble(sys, 2)
+    w, _, _ = pencil.solve_all(A, np.zeros_like(B), S)
+    np.testing.assert_allclose(w, sla.eigh(A, S, eigvals_only=True), rtol=1e-13)
+
+
+def test_p11_particle_conservation():
+    sys = gen(4, 6, 18, 30, b_scale=0.5)
+    it = dense.second_order_intermediates(sys)
+    assert abs(np.trace(it["Go"]) - np.trace(it["Gv"])) < 1e-14 * max(1.0, np.trace(it["Gv"]))
+    assert np.trace(it["Gv"]) > 0
+
+
+def test_p12_perturbative_limit():
+    """omega(lam) = Delta + lam A1_diag + O(lam^2) for non-degenerate Delta (integrals scaled by lam)."""
+    sys = gen(6, 3, 5, 8)
+    A1, _, _ = dense.assemble(sys.scaled(1.0), 1)
+    d = (sys.eps_v[None, :] - sys.eps_o[:, None]).reshape(-1)
+    order = np.argsort(d)
+    a1 = np.diag(A1)[order] - d[order]
+    for lam in (1e-3, 1e-4):
+        w, _, _ = pencil.solve_all(*dense.assemble(sys.scaled(np.sqrt(lam)), 2))
+        slope = (w - d[order]) / lam
+        np.testing.assert_allclose(slope, a1, rtol=0, atol=50 * lam * np.abs(a1).max() + 1e-9)
+
+
+# ---------------------------------------------------------------------------
+# Strengths, solver, variance
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("order", [1, 2])
+def test_strength_sum_rule(order):
+    """sum_n omega_n (mu.(X+Y)_n)^2 = mu^T S^-1 (A - B) S^-1 mu (completeness of the pencil)."""
+    sys = gen(8, 6, 20, 40, b_scale=0.4)
+    A, B, S = dense.assemble(sys, order)
+    w, X, Y = pencil.solve_all(A, B, S)
+    f = pencil.oscillator_strengths(w, X, Y, sys.dip)
+    Si = np.linalg.inv(S)
+    mu = sys.dip.reshape(3, -1)
+    rhs = (4.0 / 3.0) * sum(m @ Si @ (A - B) @ Si @ m for m in mu)
+    assert abs(f.sum() - rhs) < 1e-12 * rhs
+    # the S-normalization every root carries
+    np.testing.assert_allclose(np.einsum("ik,ij,jk->k", X, S, X) - np.einsum("ik,ij,jk->k", Y, S, Y), 1.0,
+                               atol=1e-12)
+
+
+def test_alpha_weight_minimizes_folded_quotient():
+    rng = np.random.default_rng(0)
+    for _ in range(50):
+        Z = rng.standard_normal((12, 12))
+        Z = Z + Z.T
+        v = rng.standard_normal(12)
+        v /= np.linalg.norm(v)
+        d = rng.standard_normal(12)
+
+        def rho(a):
+            x = v + a * d
+            return (x @ Z @ Z @ x) / (x @ x)
+
+        y, zd = Z @ v, Z @ d
+        al = folded.alpha_weight(y @ y, 2 * y @ zd, zd @ zd, 2 * v @ d, d @ d)
+        grid = np.linspace(-20, 20, 40001)
+        best = min(rho(a) for a in grid)
+        assert rho(al) <= best + 1e-9
+
+
+@pytest.mark.parametrize("order,o,v,naux,seed,omega0,nr", [
+    (1, 8, 24, 64, 1, 0.5, 6), (2, 8, 24, 64, 1, 0.5, 6), (2, 12, 40, 100, 7, 0.7, 8), (2, 12, 40, 100, 7, 1.3, 8)])
+def test_p8_folded_roots_equal_full_diagonalization(order, o, v, naux, seed, omega0, nr):
+    sys = gen(seed, o, v, naux)
+    A, B, S = dense.assemble(sys, order)
+    e, X, Y, f = pencil.window_solve(A, B, S, sys.dip, omega0, nr)
+    th, Xf, Yf, info = folded.folded_window_solve(A, B, S, omega0, nr)
+    assert info["converged"]
+    np.testing.assert_allclose(th, e, rtol=0, atol=1e-10)
+    f2 = pencil.oscillator_strengths(th, Xf, Yf, sys.dip)
+    np.testing.assert_allclose(f2, f, rtol=1e-6, atol=1e-12)
+
+
+def test_p9_variance_vanishes_for_converged_vectors():
+    """sigma^2 = rho_{A^2} - rho_A^2 -> 0 and sqrt(rho_{A^2}) vs rho_A has unit slope on eigenvectors."""
+    sys = gen(1, 8, 24, 64)
+    A, B, S = dense.assemble(sys, 1)
+    lam, U = np.linalg.eigh(A)
+    var = np.array([pencil.variance(A, U[:, k]) for k in range(len(lam))])
+    assert var.max() < 1e-14
+    rA = np.array([U[:, k] @ A @ U[:, k] for k in range(len(lam))])
+    rA2 = np.array([np.sqrt(U[:, k] @ A @ A @ U[:, k]) for k in range(len(lam))])
+    slope = np.polyfit(rA, rA2, 1)[0]
+    assert abs(slope - 1.0) < 1e-10
+    # a perturbed vector has a strictly positive variance
+    x = U[:, 3] + 1e-2 * U[:, 7]
+    assert pencil.variance(A, x) > 1e-8
