@@ -1,0 +1,154 @@
+/*
+ * ppwin: frequency-window solver for the first- and second-order particle-hole
+ * polarization propagator on one AMD Instinct MI355X (gfx950).
+ *
+ * The library computes, without assembling any response matrix, the product
+ * sigma = M X of the particle-hole response matrix
+ *
+ *     M = [[A, B], [B, A]],  metric Sigma = diag(S, -S)
+ *
+ * (generalized eigenvalue equation of the Theory section, "Second-order
+ * approximation of the polarization propagator") with a block of trial
+ * vectors, and drives with it the frequency-dependent inverse-Krylov /
+ * folded-spectrum solve of the subsection on interior eigenvalues: the roots of
+ * M z = omega Sigma z nearest a chosen omega0, their eigenvectors and dipole
+ * oscillator strengths.
+ *
+ * Scope: closed-shell singlet, real orbitals, density-fitted two-electron
+ * integrals (pq|rs) = sum_P B_Ppq B_Prs (Results section), particle-hole
+ * dimension N = n_occ * n_vir.  Orders: 0 (A = eps_a - eps_i, B = 0, S = 1),
+ * 1 (singlet TDHF: A1 = 2(ia|jb) - (ij|ab), B1 = 2(ia|jb) - (ib|ja)), 2 (the
+ * MP2-ground-state corrections S2, A2, B2 of the second-order equations, with the
+ * W_N cross terms included in A as in B and the symmetrized double commutator;
+ * MP2 amplitudes t_ij^ab = (ia|jb)/(eps_i + eps_j - eps_a - eps_b) are rebuilt
+ * from B in occupied strips and never stored unless requested).
+ *
+ * Conventions shared by every entry point
+ *  - particle-hole vectors are row-major [n_occ][n_vir] doubles (index i*v + a);
+ *    a 2N vector is [X; Y] = two such blocks, X first.
+ *  - unless PP_DEVICE_PTRS is given, pointers are host pointers; results are
+ *    written to caller memory only, never retained.
+ *  - every call returns a pp_status; no exception crosses the ABI.  On error the
+ *    message is kept in the handle (pp_last_error) and outputs are unspecified
+ *    unless the code says otherwise (PP_ENOTCONV writes all outputs).
+ *  - a handle is used by one host thread at a time; the server object is
+ *    thread-safe.
+ */
+#ifndef PPWIN_H
+#define PPWIN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PP_OK = 0,
+  PP_EINVAL = 1,     /* bad argument (sizes, NaN/Inf in inputs, NULL pointer) */
+  PP_ENOMEM = 2,     /* the request does not fit the HBM budget of the handle/server */
+  PP_ENOTCONV = 3,   /* solve stopped at max_cycles; outputs written, info->converged flags 0 */
+  PP_EUNSTABLE = 4,  /* A-B, A+B or S not positive definite in the subspace (complex roots) */
+  PP_EDEVICE = 5,    /* HIP runtime error; message kept */
+  PP_ENOTSUP = 6     /* option combination not supported */
+} pp_status;
+
+typedef enum {
+  PP_FP64 = 0,       /* every contraction in FP64 on FP64 matrix cores */
+  PP_FP32 = 1        /* subspace products in FP32 matrix cores, FP64 residual refinement */
+} pp_precision;
+
+/* pp_sigma flags */
+#define PP_APPLY_METRIC 1u  /* return Sigma X instead of M X */
+#define PP_DEVICE_PTRS 2u   /* X and out are device pointers */
+
+typedef struct pp_handle pp_handle;
+
+/* One closed-shell system.  All arrays are read during pp_setup only and copied
+ * into device memory the handle owns; the caller may free them on return. */
+typedef struct {
+  int32_t n_occ, n_vir, n_aux;
+  int32_t order;            /* highest order the handle serves: 0, 1 or 2 */
+  const double* eps;        /* [n_occ + n_vir] orbital energies, occupied first (Ha) */
+  const double* B_oo;       /* [n_aux][n_occ][n_occ] DF factors, symmetric in the last two */
+  const double* B_ov;       /* [n_aux][n_occ][n_vir] */
+  const double* B_vv;       /* [n_aux][n_vir][n_vir], symmetric in the last two */
+  const double* dip;        /* [3][n_occ][n_vir] dipole integrals (NULL: no strengths) */
+  int32_t device_ptrs;      /* nonzero: the arrays above are device pointers */
+} pp_system;
+
+typedef struct {
+  int32_t precision;        /* pp_precision used by the subspace products (default FP64) */
+  int32_t store_amplitudes; /* 1: keep all amplitude strips (o^2 v^2 doubles); 0: rebuild per
+                               product; -1 (default): keep them when they fit the budget */
+  int32_t strip_rows;       /* occupied rows per amplitude strip (0 = chosen from the budget) */
+  double tol;               /* residual tolerance |(M - theta Sigma) y| / |y| (default 1e-9) */
+  int32_t block;            /* block size (0: n_roots + max(2, n_roots/2)) */
+  int32_t krylov_steps;     /* basis vectors per cycle: corrections + (krylov_steps-1)
+                               weighted-Jacobi steps (default 2) */
+  int32_t max_basis;        /* largest subspace (default 400, at most 512) */
+  int32_t max_cycles;       /* default 200 */
+  double d_clamp;           /* smallest |diagonal| of the Jacobi splitting (default 1e-4 Ha) */
+  uint64_t hbm_budget;      /* bytes the handle may allocate (0: 90% of free device memory) */
+  int32_t device;           /* HIP device ordinal */
+  void* stream;             /* hipStream_t to run on (NULL: a stream owned by the handle) */
+  uint64_t seed;            /* start-block perturbation seed */
+} pp_options;
+
+#define PP_MAX_ROOTS 64
+
+typedef struct {
+  int32_t cycles;               /* restart cycles used */
+  int32_t basis;                /* final subspace size */
+  int64_t products;             /* particle-hole vectors multiplied by (A, B, S) */
+  int32_t n_roots;
+  int32_t converged[PP_MAX_ROOTS];
+  double residual[PP_MAX_ROOTS];  /* FP64 |(M - theta Sigma) y| / |y| per returned root */
+  double seconds;               /* wall time of the solve */
+  double sigma_seconds;         /* time inside the product kernels (device events) */
+  double sigma_flops;           /* algorithmic flops of those products */
+} pp_solve_info;
+
+/* Fills *opt with the defaults documented above. */
+void pp_default_options(pp_options* opt);
+
+/* Copies the system to the device and builds what every product needs: layouts
+ * of the DF factors, the Jacobi diagonal and, at order 2, the MP2 intermediates
+ * (occupied/virtual MP2 density and energy-weighted density, the ring
+ * intermediate Lambda_P,ia = sum_kc tau_ik^ac B_P,kc) from amplitude strips.
+ * Returns PP_EINVAL for bad sizes or non-finite inputs, PP_ENOMEM when the
+ * footprint exceeds opt->hbm_budget, PP_EDEVICE on a HIP error.  *out is NULL
+ * on failure.  opt may be NULL (defaults). */
+pp_status pp_setup(const pp_system* sys, const pp_options* opt, pp_handle** out);
+
+/* out = M X (or Sigma X with PP_APPLY_METRIC) for m 2N-vectors.  X and out are
+ * [m][2][n_occ][n_vir]; order (0..2) must not exceed the setup order.
+ * Synchronous.  The same precision as the handle's FP64 path is used. */
+pp_status pp_sigma(pp_handle* h, int32_t order, int32_t m, const double* X, double* out, uint32_t flags);
+
+/* Roots of M z = omega Sigma z nearest omega0 on the positive branch, at the
+ * handle's setup order: energies[n_roots] ascending (Ha); vectors
+ * [n_roots][2][n_occ][n_vir] with X^T S X - Y^T S Y = 1 (nullable); osc
+ * [n_roots] dipole oscillator strengths f = (2/3) omega sum_x (sqrt(2) mu^x.(X+Y))^2
+ * (nullable; needs dip at setup); info (nullable).  1 <= n_roots <= min(64, N). */
+pp_status pp_window_solve(pp_handle* h, double omega0, int32_t n_roots, double* energies, double* vectors,
+                          double* osc, pp_solve_info* info);
+
+/* MP2 correlation energy sum tau_ij^ab (ia|jb) found during an order-2 setup (0 otherwise). */
+double pp_mp2_energy(const pp_handle* h);
+
+/* Device bytes owned by the handle. */
+uint64_t pp_device_bytes(const pp_handle* h);
+
+/* Frees every device allocation of the handle.  NULL is accepted. */
+pp_status pp_destroy(pp_handle* h);
+
+const char* pp_status_string(pp_status s);
+/* Last error message of the handle (NULL handle: last error of pp_setup in this thread). */
+const char* pp_last_error(const pp_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PPWIN_H */

@@ -1,0 +1,47 @@
+/*
+ * Internal entry points of the ppwin library that the test-suite calls to check
+ * single building blocks against plain references.  They are exported with the
+ * ppint_ prefix, take device pointers, run synchronously on the default stream
+ * and return a pp_status like the public API.  They are not part of the stable
+ * interface.
+ */
+#ifndef PPWIN_TESTING_H
+#define PPWIN_TESTING_H
+
+#include <stdint.h>
+
+#include "ppwin.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* C[b](m,n) = alpha * sum_kb sum_k A(m,k) B(k,n) + beta * C, the library GEMM
+ * (layouts as in the library: transA = 0 -> A[m*lda+k], 1 -> A[k*lda+m]; transB = 0
+ * -> B[k*ldb+n], 1 -> B[n*ldb+k]; batch b offsets b*sA, b*sB, b*sC; outer reduction
+ * kb offsets kb*sAk, kb*sBk).  fp32 != 0 runs the FP32 matrix-core kernel on
+ * float arrays.  ws_bytes of scratch are allocated for split-K (0 = no split). */
+pp_status ppint_gemm(int32_t fp32, int32_t M, int32_t N, int32_t K, int32_t KB, int32_t nbatch, int32_t transA,
+                     int64_t lda, int64_t sA, int64_t sAk, int32_t transB, int64_t ldb, int64_t sB, int64_t sBk,
+                     int64_t ldc, int64_t sC, double alpha, const void* A, const void* B, double beta, void* C,
+                     uint64_t ws_bytes);
+
+/* Symmetric eigen-decomposition of an n x n row-major matrix A (device, lda = n)
+ * by the library's one-workgroup FP64 solver: w ascending, Z columns = vectors
+ * (row-major n x n, Z[r*n + c] = component r of vector c). */
+pp_status ppint_syev(int32_t n, const double* A, double* w, double* Z);
+
+/* Lower Cholesky factor of an SPD n x n matrix (device, row-major), in L. */
+pp_status ppint_cholesky(int32_t n, const double* A, double* L);
+
+/* Products of k particle-hole vectors by A, B, S at the given order (device
+ * pointers, [k][n_occ][n_vir] each; SV may be NULL). fp32 selects the FP32
+ * matrix-core path. */
+pp_status ppint_products(pp_handle* h, int32_t order, int32_t k, const double* V, double* AV, double* BV,
+                         double* SV, int32_t fp32);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PPWIN_TESTING_H */

@@ -1,0 +1,218 @@
+"""ctypes binding of libppwin (argument marshalling only).
+
+Every computation happens in the HIP library; this module converts numpy arrays
+and torch device tensors into the plain pointers and sizes of the C ABI declared
+in include/ppwin.h and include/ppwin_testing.h.  Loading fails loudly when the
+library has not been built: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libppwin.so")
+
+PP_OK, PP_EINVAL, PP_ENOMEM, PP_ENOTCONV, PP_EUNSTABLE, PP_EDEVICE, PP_ENOTSUP = range(7)
+PP_FP64, PP_FP32 = 0, 1
+PP_APPLY_METRIC = 1
+PP_DEVICE_PTRS = 2
+PP_MAX_ROOTS = 64
+
+
+class PPError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+class pp_system(C.Structure):
+    _fields_ = [("n_occ", C.c_int32), ("n_vir", C.c_int32), ("n_aux", C.c_int32), ("order", C.c_int32),
+                ("eps", C.c_void_p), ("B_oo", C.c_void_p), ("B_ov", C.c_void_p), ("B_vv", C.c_void_p),
+                ("dip", C.c_void_p), ("device_ptrs", C.c_int32)]
+
+
+class pp_options(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("store_amplitudes", C.c_int32), ("strip_rows", C.c_int32),
+                ("tol", C.c_double), ("block", C.c_int32), ("krylov_steps", C.c_int32),
+                ("max_basis", C.c_int32), ("max_cycles", C.c_int32), ("d_clamp", C.c_double),
+                ("hbm_budget", C.c_uint64), ("device", C.c_int32), ("stream", C.c_void_p),
+                ("seed", C.c_uint64)]
+
+
+class pp_solve_info(C.Structure):
+    _fields_ = [("cycles", C.c_int32), ("basis", C.c_int32), ("products", C.c_int64), ("n_roots", C.c_int32),
+                ("converged", C.c_int32 * PP_MAX_ROOTS), ("residual", C.c_double * PP_MAX_ROOTS),
+                ("seconds", C.c_double), ("sigma_seconds", C.c_double), ("sigma_flops", C.c_double)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libppwin.so not found at {LIB_PATH}: run __graft_entry__.build() first")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, u32, u64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_double
+        L.pp_default_options.argtypes = [C.POINTER(pp_options)]
+        L.pp_default_options.restype = None
+        L.pp_setup.argtypes = [C.POINTER(pp_system), C.POINTER(pp_options), C.POINTER(vp)]
+        L.pp_setup.restype = C.c_int
+        L.pp_sigma.argtypes = [vp, i32, i32, vp, vp, u32]
+        L.pp_sigma.restype = C.c_int
+        L.pp_window_solve.argtypes = [vp, dbl, i32, vp, vp, vp, C.POINTER(pp_solve_info)]
+        L.pp_window_solve.restype = C.c_int
+        L.pp_mp2_energy.argtypes = [vp]
+        L.pp_mp2_energy.restype = dbl
+        L.pp_device_bytes.argtypes = [vp]
+        L.pp_device_bytes.restype = u64
+        L.pp_destroy.argtypes = [vp]
+        L.pp_destroy.restype = C.c_int
+        L.pp_status_string.argtypes = [C.c_int]
+        L.pp_status_string.restype = C.c_char_p
+        L.pp_last_error.argtypes = [vp]
+        L.pp_last_error.restype = C.c_char_p
+        L.ppint_gemm.argtypes = [i32, i32, i32, i32, i32, i32, i32, i64, i64, i64, i32, i64, i64, i64, i64, i64,
+                                 dbl, vp, vp, dbl, vp, u64]
+        L.ppint_gemm.restype = C.c_int
+        L.ppint_syev.argtypes = [i32, vp, vp, vp]
+        L.ppint_syev.restype = C.c_int
+        L.ppint_cholesky.argtypes = [i32, vp, vp]
+        L.ppint_cholesky.restype = C.c_int
+        L.ppint_products.argtypes = [vp, i32, i32, vp, vp, vp, vp, i32]
+        L.ppint_products.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(st: int, handle=None):
+    if st != PP_OK:
+        L = lib()
+        msg = L.pp_last_error(handle).decode() if handle is not None else L.pp_last_error(None).decode()
+        raise PPError(st, f"{L.pp_status_string(st).decode()}: {msg}")
+
+
+def default_options(**kw) -> pp_options:
+    o = pp_options()
+    lib().pp_default_options(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class Handle:
+    """A system set up on the device (wraps pp_handle*)."""
+
+    def __init__(self, eps, B_oo, B_ov, B_vv, dip=None, order: int = 2, options: Optional[pp_options] = None, **kw):
+        L = lib()
+        self._arrays = [_f64(eps), _f64(B_oo), _f64(B_ov), _f64(B_vv)] + ([_f64(dip)] if dip is not None else [])
+        naux, o, v = self._arrays[2].shape
+        s = pp_system(n_occ=o, n_vir=v, n_aux=naux, order=order, eps=self._arrays[0].ctypes.data,
+                      B_oo=self._arrays[1].ctypes.data, B_ov=self._arrays[2].ctypes.data,
+                      B_vv=self._arrays[3].ctypes.data,
+                      dip=self._arrays[4].ctypes.data if dip is not None else None, device_ptrs=0)
+        opt = options if options is not None else default_options(**kw)
+        h = C.c_void_p()
+        st = L.pp_setup(C.byref(s), C.byref(opt), C.byref(h))
+        self._arrays = None
+        _check(st)
+        self.h = h
+        self.o, self.v, self.naux, self.order = o, v, naux, order
+        self.N = o * v
+
+    @classmethod
+    def from_system(cls, sys, order: int = 2, **kw):
+        return cls(sys.eps, sys.B_oo, sys.B_ov, sys.B_vv, sys.dip, order=order, **kw)
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().pp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def sigma(self, X, order: Optional[int] = None, metric: bool = False) -> np.ndarray:
+        """M X (or Sigma X) for host X of shape [m][2][o][v] or [m][2][N]."""
+        X = _f64(X)
+        m = X.shape[0]
+        out = np.empty((m, 2, self.N))
+        st = lib().pp_sigma(self.h, self.order if order is None else order, m, X.ctypes.data, out.ctypes.data,
+                            PP_APPLY_METRIC if metric else 0)
+        _check(st, self.h)
+        return out
+
+    def sigma_device(self, X, out, order: Optional[int] = None, metric: bool = False):
+        """Same as sigma() on torch device tensors (no host copies)."""
+        m = X.shape[0]
+        flags = PP_DEVICE_PTRS | (PP_APPLY_METRIC if metric else 0)
+        st = lib().pp_sigma(self.h, self.order if order is None else order, m, X.data_ptr(), out.data_ptr(), flags)
+        _check(st, self.h)
+
+    def products(self, V, AV, BV, SV=None, order: Optional[int] = None, fp32: bool = False):
+        """A V, B V, S V for torch device tensors [k][N] (internal test hook)."""
+        st = lib().ppint_products(self.h, self.order if order is None else order, V.shape[0], V.data_ptr(),
+                                  AV.data_ptr(), BV.data_ptr(), SV.data_ptr() if SV is not None else None,
+                                  1 if fp32 else 0)
+        _check(st, self.h)
+
+    def window_solve(self, omega0: float, n_roots: int, vectors: bool = True, osc: bool = True,
+                     allow_unconverged: bool = False):
+        """Returns (energies, vectors [r][2][N] or None, osc or None, info dict)."""
+        e = np.empty(n_roots)
+        vec = np.empty((n_roots, 2, self.N)) if vectors else None
+        f = np.empty(n_roots) if osc else None
+        info = pp_solve_info()
+        st = lib().pp_window_solve(self.h, float(omega0), n_roots, e.ctypes.data,
+                                   vec.ctypes.data if vec is not None else None,
+                                   f.ctypes.data if f is not None else None, C.byref(info))
+        if not (st == PP_ENOTCONV and allow_unconverged):
+            _check(st, self.h)
+        d = dict(cycles=info.cycles, basis=info.basis, products=info.products, seconds=info.seconds,
+                 sigma_seconds=info.sigma_seconds, sigma_flops=info.sigma_flops,
+                 residual=np.array(info.residual[:n_roots]), converged=np.array(info.converged[:n_roots]),
+                 status=st)
+        return e, vec, f, d
+
+    def mp2_energy(self) -> float:
+        return lib().pp_mp2_energy(self.h)
+
+    def device_bytes(self) -> int:
+        return int(lib().pp_device_bytes(self.h))
+
+
+def gemm(A, B, C_, *, M, N, K, KB=1, nbatch=1, transA=0, lda, sA=0, sAk=0, transB=0, ldb, sB=0, sBk=0, ldc,
+         sC=0, alpha=1.0, beta=0.0, ws_bytes=0, fp32=False):
+    """Library GEMM on torch device tensors (internal test hook)."""
+    st = lib().ppint_gemm(1 if fp32 else 0, M, N, K, KB, nbatch, transA, lda, sA, sAk, transB, ldb, sB, sBk, ldc, sC,
+                          alpha, A.data_ptr(), B.data_ptr(), beta, C_.data_ptr(), ws_bytes)
+    _check(st)
+
+
+def syev(A, w, Z):
+    _check(lib().ppint_syev(A.shape[0], A.data_ptr(), w.data_ptr(), Z.data_ptr()))
+
+
+def cholesky(A, L_):
+    _check(lib().ppint_cholesky(A.shape[0], A.data_ptr(), L_.data_ptr()))

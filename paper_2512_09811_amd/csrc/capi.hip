@@ -1,0 +1,305 @@
+// C ABI of the ppwin library: argument checks, error translation, host<->device
+// marshalling.  No exception leaves this file.
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ppwin.h"
+#include "../../include/ppwin_testing.h"
+#include "context.h"
+#include "kernels.h"
+#include "solver.h"
+
+struct pp_handle {
+  ppw::Context* ctx = nullptr;
+  pp_options opt{};
+  std::string err;
+};
+
+namespace {
+
+thread_local std::string g_setup_error;
+
+template <typename F>
+pp_status guarded(std::string* err, F&& f) {
+  try {
+    f();
+    return PP_OK;
+  } catch (const ppw::InvalidArg& e) {
+    if (err) *err = e.what();
+    return PP_EINVAL;
+  } catch (const ppw::OutOfBudget& e) {
+    if (err) *err = e.what();
+    return PP_ENOMEM;
+  } catch (const ppw::NotConverged& e) {
+    if (err) *err = e.what();
+    return PP_ENOTCONV;
+  } catch (const ppw::Unstable& e) {
+    if (err) *err = e.what();
+    return PP_EUNSTABLE;
+  } catch (const ppw::NotSupported& e) {
+    if (err) *err = e.what();
+    return PP_ENOTSUP;
+  } catch (const ppw::DeviceError& e) {
+    if (err) *err = e.what();
+    return PP_EDEVICE;
+  } catch (const std::exception& e) {
+    if (err) *err = e.what();
+    return PP_EDEVICE;
+  } catch (...) {
+    if (err) *err = "unknown error";
+    return PP_EDEVICE;
+  }
+}
+
+void check_finite(const double* p, size_t n, const char* what) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) throw ppw::InvalidArg(std::string("non-finite value in ") + what);
+}
+
+}  // namespace
+
+extern "C" {
+
+void pp_default_options(pp_options* opt) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->precision = PP_FP64;
+  opt->store_amplitudes = -1;
+  opt->strip_rows = 0;
+  opt->tol = 1e-9;
+  opt->block = 0;
+  opt->krylov_steps = 2;
+  opt->max_basis = 400;
+  opt->max_cycles = 200;
+  opt->d_clamp = 1e-4;
+  opt->hbm_budget = 0;
+  opt->device = 0;
+  opt->stream = nullptr;
+  opt->seed = 0;
+}
+
+pp_status pp_setup(const pp_system* sys, const pp_options* opt_in, pp_handle** out) {
+  if (out) *out = nullptr;
+  g_setup_error.clear();
+  pp_handle* h = nullptr;
+  pp_status st = guarded(&g_setup_error, [&] {
+    if (!sys || !out) throw ppw::InvalidArg("sys and out must not be NULL");
+    pp_options opt;
+    pp_default_options(&opt);
+    if (opt_in) opt = *opt_in;
+    if (opt.precision != PP_FP64 && opt.precision != PP_FP32) throw ppw::InvalidArg("unknown precision");
+    if (opt.max_basis > 512) throw ppw::InvalidArg("max_basis must be <= 512");
+    if (!(opt.tol > 0)) throw ppw::InvalidArg("tol must be positive");
+    const int o = sys->n_occ, v = sys->n_vir, X = sys->n_aux;
+    if (o < 1 || v < 1 || X < 1) throw ppw::InvalidArg("n_occ, n_vir and n_aux must be positive");
+    if (!sys->eps || !sys->B_oo || !sys->B_ov || !sys->B_vv) throw ppw::InvalidArg("NULL input array");
+    if (!sys->device_ptrs) {
+      const size_t N = (size_t)o * v;
+      check_finite(sys->eps, (size_t)o + v, "eps");
+      check_finite(sys->B_oo, (size_t)X * o * o, "B_oo");
+      check_finite(sys->B_ov, (size_t)X * N, "B_ov");
+      check_finite(sys->B_vv, (size_t)X * v * v, "B_vv");
+      if (sys->dip) check_finite(sys->dip, 3 * N, "dip");
+      for (int i = 0; i + 1 < o; ++i)
+        if (sys->eps[i] > sys->eps[i + 1]) throw ppw::InvalidArg("occupied energies must be ascending");
+      if (sys->eps[o - 1] >= sys->eps[o]) throw ppw::InvalidArg("occupied energies must lie below virtual ones");
+    }
+    ppw::SetupParams p;
+    p.o = o;
+    p.v = v;
+    p.naux = X;
+    p.order = sys->order;
+    p.eps = sys->eps;
+    p.Boo = sys->B_oo;
+    p.Bov = sys->B_ov;
+    p.Bvv = sys->B_vv;
+    p.dip = sys->dip;
+    p.device_ptrs = sys->device_ptrs != 0;
+    p.store_amplitudes = opt.store_amplitudes;
+    p.strip_rows = opt.strip_rows;
+    p.want_f32 = opt.precision == PP_FP32;
+    p.budget = opt.hbm_budget;
+    p.device = opt.device;
+    p.stream = static_cast<hipStream_t>(opt.stream);
+    h = new pp_handle();
+    h->opt = opt;
+    h->ctx = ppw::setup_context(p);
+    *out = h;
+  });
+  if (st != PP_OK && h) {
+    delete h->ctx;
+    delete h;
+    if (out) *out = nullptr;
+  }
+  return st;
+}
+
+pp_status pp_sigma(pp_handle* h, int32_t order, int32_t m, const double* X, double* outp, uint32_t flags) {
+  if (!h || !h->ctx) return PP_EINVAL;
+  return guarded(&h->err, [&] {
+    ppw::Context& c = *h->ctx;
+    if (m < 0) throw ppw::InvalidArg("m must be >= 0");
+    if (order < 0 || order > c.order) throw ppw::InvalidArg("order exceeds the setup order");
+    if (m == 0) return;
+    if (!X || !outp) throw ppw::InvalidArg("NULL vector pointer");
+    PPW_HIP(hipSetDevice(c.device));
+    const long N = c.N;
+    const bool dev = (flags & PP_DEVICE_PTRS) != 0;
+    const int k = 2 * m;
+    double* V = c.arena.alloc<double>((size_t)k * N, "sigma V");
+    double* AV = c.arena.alloc<double>((size_t)k * N, "sigma AV");
+    double* BV = c.arena.alloc<double>((size_t)k * N, "sigma BV");
+    double* SV = c.arena.alloc<double>((size_t)k * N, "sigma SV");
+    double* out = dev ? outp : c.arena.alloc<double>((size_t)2 * m * N, "sigma out");
+    struct Free {
+      ppw::Context& c;
+      std::vector<void*> p;
+      ~Free() {
+        for (void* q : p) c.arena.free(q);
+      }
+    } fr{c, {V, AV, BV, SV}};
+    if (!dev) fr.p.push_back(out);
+    const hipMemcpyKind kin = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    PPW_HIP(hipMemcpy2DAsync(V, N * sizeof(double), X, 2 * N * sizeof(double), N * sizeof(double), m, kin,
+                             c.stream));
+    PPW_HIP(hipMemcpy2DAsync(V + (size_t)m * N, N * sizeof(double), X + N, 2 * N * sizeof(double),
+                             N * sizeof(double), m, kin, c.stream));
+    const bool metric = (flags & PP_APPLY_METRIC) != 0;
+    ppw::sigma_core(c, order, k, V, AV, BV, SV);
+    ppw::combine_pairs(N, m, AV, BV, SV, metric, out, c.stream);
+    if (!dev)
+      PPW_HIP(hipMemcpyAsync(outp, out, sizeof(double) * 2 * m * N, hipMemcpyDeviceToHost, c.stream));
+    PPW_HIP(hipStreamSynchronize(c.stream));
+  });
+}
+
+pp_status pp_window_solve(pp_handle* h, double omega0, int32_t n_roots, double* energies, double* vectors,
+                          double* osc, pp_solve_info* info) {
+  if (!h || !h->ctx) return PP_EINVAL;
+  return guarded(&h->err, [&] {
+    if (!std::isfinite(omega0)) throw ppw::InvalidArg("omega0 must be finite");
+    if (n_roots < 1 || n_roots > PP_MAX_ROOTS || n_roots > h->ctx->N)
+      throw ppw::InvalidArg("n_roots out of range");
+    if (!energies) throw ppw::InvalidArg("energies must not be NULL");
+    if (osc && !h->ctx->dip) throw ppw::InvalidArg("oscillator strengths need dipole integrals at setup");
+    ppw::SolveOptions so;
+    so.precision = h->opt.precision;
+    so.tol = h->opt.tol;
+    so.block = h->opt.block;
+    so.krylov_steps = h->opt.krylov_steps;
+    so.max_basis = h->opt.max_basis;
+    so.max_cycles = h->opt.max_cycles;
+    so.d_clamp = h->opt.d_clamp;
+    so.seed = h->opt.seed;
+    ppw::window_solve(*h->ctx, so, omega0, n_roots, energies, vectors, osc, info);
+  });
+}
+
+double pp_mp2_energy(const pp_handle* h) { return (h && h->ctx) ? h->ctx->emp2 : 0.0; }
+
+uint64_t pp_device_bytes(const pp_handle* h) { return (h && h->ctx) ? h->ctx->arena.used() : 0; }
+
+pp_status pp_destroy(pp_handle* h) {
+  if (!h) return PP_OK;
+  std::string dummy;
+  pp_status st = guarded(&dummy, [&] {
+    if (h->ctx) (void)hipSetDevice(h->ctx->device);
+    delete h->ctx;
+    h->ctx = nullptr;
+  });
+  delete h;
+  return st;
+}
+
+const char* pp_status_string(pp_status s) {
+  switch (s) {
+    case PP_OK: return "PP_OK";
+    case PP_EINVAL: return "PP_EINVAL: invalid argument";
+    case PP_ENOMEM: return "PP_ENOMEM: device memory budget exceeded";
+    case PP_ENOTCONV: return "PP_ENOTCONV: solve did not converge";
+    case PP_EUNSTABLE: return "PP_EUNSTABLE: response matrix not positive definite";
+    case PP_EDEVICE: return "PP_EDEVICE: HIP runtime error";
+    case PP_ENOTSUP: return "PP_ENOTSUP: not supported";
+  }
+  return "unknown status";
+}
+
+const char* pp_last_error(const pp_handle* h) {
+  if (!h) return g_setup_error.c_str();
+  return h->err.c_str();
+}
+
+// ---------------------------------------------------------------------------
+// test hooks
+// ---------------------------------------------------------------------------
+pp_status ppint_gemm(int32_t fp32, int32_t M, int32_t N, int32_t K, int32_t KB, int32_t nbatch, int32_t transA,
+                     int64_t lda, int64_t sA, int64_t sAk, int32_t transB, int64_t ldb, int64_t sB, int64_t sBk,
+                     int64_t ldc, int64_t sC, double alpha, const void* A, const void* B, double beta, void* C,
+                     uint64_t ws_bytes) {
+  std::string err;
+  void* ws = nullptr;
+  pp_status st = guarded(&err, [&] {
+    ppw::GemmDesc d;
+    d.M = M;
+    d.N = N;
+    d.K = K;
+    d.KB = KB;
+    d.nb1 = nbatch;
+    d.transA = transA;
+    d.lda = lda;
+    d.sA1 = sA;
+    d.sAk = sAk;
+    d.transB = transB;
+    d.ldb = ldb;
+    d.sB1 = sB;
+    d.sBk = sBk;
+    d.ldc = ldc;
+    d.sC1 = sC;
+    ppw::Workspace w;
+    if (ws_bytes) {
+      PPW_HIP(hipMalloc(&ws, ws_bytes));
+      w.ptr = ws;
+      w.bytes = ws_bytes;
+    }
+    if (fp32)
+      ppw::gemm_f32(d, (float)alpha, (const float*)A, (const float*)B, (float)beta, (float*)C, nullptr, w);
+    else
+      ppw::gemm_f64(d, alpha, (const double*)A, (const double*)B, beta, (double*)C, nullptr, w);
+    PPW_HIP(hipDeviceSynchronize());
+  });
+  if (ws) (void)hipFree(ws);
+  return st;
+}
+
+pp_status ppint_syev(int32_t n, const double* A, double* w, double* Z) {
+  std::string err;
+  return guarded(&err, [&] {
+    ppw::small_syev(n, A, w, Z, nullptr);
+    PPW_HIP(hipDeviceSynchronize());
+  });
+}
+
+pp_status ppint_cholesky(int32_t n, const double* A, double* L) {
+  std::string err;
+  return guarded(&err, [&] {
+    ppw::small_cholesky(n, A, L, nullptr, nullptr);
+    PPW_HIP(hipDeviceSynchronize());
+  });
+}
+
+pp_status ppint_products(pp_handle* h, int32_t order, int32_t k, const double* V, double* AV, double* BV, double* SV,
+                         int32_t fp32) {
+  if (!h || !h->ctx) return PP_EINVAL;
+  return guarded(&h->err, [&] {
+    if (order < 0 || order > h->ctx->order) throw ppw::InvalidArg("order exceeds the setup order");
+    if (fp32)
+      ppw::sigma_core_f32(*h->ctx, order, k, V, AV, BV, SV);
+    else
+      ppw::sigma_core(*h->ctx, order, k, V, AV, BV, SV);
+    PPW_HIP(hipStreamSynchronize(h->ctx->stream));
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,81 @@
+// Shared declarations of the ppwin HIP library (gfx950 / CDNA4 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+
+namespace ppw {
+
+// Error raised inside the library; converted to a pp_status at the C ABI.
+struct DeviceError : std::runtime_error {
+  explicit DeviceError(const std::string& m) : std::runtime_error(m) {}
+};
+struct InvalidArg : std::runtime_error {
+  explicit InvalidArg(const std::string& m) : std::runtime_error(m) {}
+};
+struct OutOfBudget : std::runtime_error {
+  explicit OutOfBudget(const std::string& m) : std::runtime_error(m) {}
+};
+struct NotConverged : std::runtime_error {
+  explicit NotConverged(const std::string& m) : std::runtime_error(m) {}
+};
+struct Unstable : std::runtime_error {
+  explicit Unstable(const std::string& m) : std::runtime_error(m) {}
+};
+struct NotSupported : std::runtime_error {
+  explicit NotSupported(const std::string& m) : std::runtime_error(m) {}
+};
+
+#define PPW_HIP(call)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      throw ::ppw::DeviceError(std::string(#call) + ": " + hipGetErrorString(e_));       \
+  } while (0)
+
+#define PPW_LAUNCH_CHECK() PPW_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------------------
+// Batched, strided GEMM with an outer reduction loop.
+//
+//   C[b1,b2](m, n) = alpha * sum_{kb < KB} sum_{k < K} A[b1,b2,kb](m, k) B[b1,b2,kb](k, n)
+//                    + beta * C[b1,b2](m, n)
+//
+// A(m,k) = A[m*lda + k] (transA = 0) or A[k*lda + m] (transA = 1), offset by
+// b1*sA1 + b2*sA2 + kb*sAk elements; likewise B(k,n) = B[k*ldb + n] (transB = 0)
+// or B[n*ldb + k] (transB = 1).  C(m,n) = C[m*ldc + n] + b1*sC1 + b2*sC2.
+// beta == 0 never reads C.  The outer loop lets a contraction index that is
+// split across two strides (e.g. (j, P) with P between j and the inner index)
+// be reduced without a transpose.
+// ---------------------------------------------------------------------------
+struct GemmDesc {
+  int M = 0, N = 0, K = 0, KB = 1;
+  int nb1 = 1, nb2 = 1;
+  int transA = 0, transB = 0;
+  long lda = 0, ldb = 0, ldc = 0;
+  long sA1 = 0, sA2 = 0, sAk = 0;
+  long sB1 = 0, sB2 = 0, sBk = 0;
+  long sC1 = 0, sC2 = 0;
+};
+
+// Workspace used by split-K launches (owned by the caller, bytes).
+struct Workspace {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+void gemm_f64(const GemmDesc& d, double alpha, const double* A, const double* B, double beta,
+              double* C, hipStream_t s, Workspace ws = {});
+void gemm_f32(const GemmDesc& d, float alpha, const float* A, const float* B, float beta, float* C,
+              hipStream_t s, Workspace ws = {});
+
+// Algorithmic flop count of a GemmDesc (2 per multiply-add).
+inline double gemm_flops(const GemmDesc& d) {
+  return 2.0 * d.M * (double)d.N * d.K * d.KB * d.nb1 * d.nb2;
+}
+
+}  // namespace ppw

@@ -1,0 +1,152 @@
+// Device-resident state of one system (the object behind a pp_handle).
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace ppw {
+
+// Device allocations with a byte budget.  Every allocation of a handle goes
+// through its arena, so the footprint is known and bounded.
+class Arena {
+ public:
+  explicit Arena(size_t budget = 0) : budget_(budget) {}
+  ~Arena() { release(); }
+  Arena(const Arena&) = delete;
+  Arena& operator=(const Arena&) = delete;
+
+  void set_budget(size_t b) { budget_ = b; }
+  size_t used() const { return used_; }
+  size_t budget() const { return budget_; }
+
+  template <typename T>
+  T* alloc(size_t n, const char* what) {
+    const size_t bytes = ((n * sizeof(T) + 255) / 256) * 256;
+    if (budget_ && used_ + bytes > budget_)
+      throw OutOfBudget(std::string("device budget exceeded allocating ") + what + " (" +
+                        std::to_string(bytes) + " B, " + std::to_string(used_) + " of " +
+                        std::to_string(budget_) + " B in use)");
+    void* p = nullptr;
+    if (bytes) {
+      hipError_t e = hipMalloc(&p, bytes);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw OutOfBudget(std::string("hipMalloc failed for ") + what + ": " + hipGetErrorString(e));
+      }
+    }
+    blocks_.push_back({p, bytes});
+    used_ += bytes;
+    return static_cast<T*>(p);
+  }
+  void free(void* p) {
+    for (size_t i = 0; i < blocks_.size(); ++i)
+      if (blocks_[i].p == p) {
+        if (p) (void)hipFree(p);
+        used_ -= blocks_[i].bytes;
+        blocks_.erase(blocks_.begin() + i);
+        return;
+      }
+  }
+  void release() {
+    for (auto& b : blocks_)
+      if (b.p) (void)hipFree(b.p);
+    blocks_.clear();
+    used_ = 0;
+  }
+
+ private:
+  struct Block {
+    void* p;
+    size_t bytes;
+  };
+  std::vector<Block> blocks_;
+  size_t used_ = 0;
+  size_t budget_ = 0;
+};
+
+struct SetupParams {
+  int o = 0, v = 0, naux = 0, order = 1;
+  const double *eps = nullptr, *Boo = nullptr, *Bov = nullptr, *Bvv = nullptr, *dip = nullptr;
+  bool device_ptrs = false;
+  int store_amplitudes = -1;  // -1 auto
+  int strip_rows = 0;
+  bool want_f32 = false;       // keep FP32 copies for the reduced-precision product path
+  size_t budget = 0;
+  int device = 0;
+  hipStream_t stream = nullptr;
+};
+
+// Timing/flop accounting of product passes.
+struct SigmaStats {
+  double flops = 0.0;       // algorithmic flops issued by product passes
+  double seconds = 0.0;     // device time of product passes (events)
+  long vectors = 0;         // particle-hole vectors multiplied
+  double hhat_flops = 0.0;  // flops of the amplitude-weighted contraction (dominant kernel)
+  double hhat_seconds = 0.0;
+  long hhat_launches = 0;
+};
+
+struct Context {
+  int o = 0, v = 0, naux = 0, order = 0;
+  long N = 0;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  Arena arena;
+
+  // inputs (device)
+  double *eps_o = nullptr, *eps_v = nullptr;
+  double *Bov = nullptr, *Boo = nullptr, *Bvv = nullptr, *dip = nullptr;
+  // derived layouts
+  double* BovLam = nullptr;  // [ns][naux][N]: Bov, then Lambda at order 2
+  double* Lam = nullptr;     // Lambda_P,ia = sum_kc tau_ik^ac B_P,kc
+  double* Boo_t = nullptr;   // [o][o][naux]
+  double* R = nullptr;       // [o][ns][naux][v] ring operand
+  int ns = 1;
+  // second-order intermediates
+  double *Gv = nullptr, *Ev = nullptr, *Go = nullptr, *Eo = nullptr;
+  // diagonals of A, B (first order part) and S
+  double *dA = nullptr, *dB = nullptr, *dS = nullptr;
+  // stored amplitudes tau[(i,c)][(j,d)] (optional)
+  double* tau = nullptr;
+  int strip_rows = 0;
+  double emp2 = 0.0;
+
+  // FP32 copies for the reduced-precision path (optional)
+  float *Bov32 = nullptr, *Boo32 = nullptr, *Bvv32 = nullptr, *BovLam32 = nullptr, *Boo_t32 = nullptr,
+        *R32 = nullptr, *tau32 = nullptr;
+  float *Gv32 = nullptr, *Ev32 = nullptr, *Go32 = nullptr, *Eo32 = nullptr;
+
+  // product workspace (grown on demand)
+  int kcap = 0;
+  int kcap32 = 0;
+  double *w_c = nullptr, *w_J = nullptr, *w_G = nullptr, *w_U = nullptr, *w_H = nullptr, *w_S = nullptr,
+         *w_tau = nullptr, *w_P = nullptr;
+  float *w32_V = nullptr, *w32_c = nullptr, *w32_J = nullptr, *w32_G = nullptr, *w32_U = nullptr,
+        *w32_H = nullptr, *w32_S = nullptr, *w32_tau = nullptr, *w32_P = nullptr, *w32_AV = nullptr,
+        *w32_BV = nullptr;
+  Workspace ws;      // split-K workspace
+  size_t ws_bytes = 0;
+
+  SigmaStats stats;
+  std::string last_error;
+
+  ~Context();
+};
+
+// Builds a context (copies inputs, layouts, diagonals, MP2 intermediates).
+Context* setup_context(const SetupParams& p);
+
+// Products of k particle-hole vectors V ([k][o][v], device): AV = A V, BV = B V,
+// SV = S V (SV may be null) at the given order (<= ctx order).  Device pointers.
+void sigma_core(Context& c, int order, int k, const double* V, double* AV, double* BV, double* SV);
+
+// Same products with the contractions on FP32 matrix cores (V and outputs FP64).
+void sigma_core_f32(Context& c, int order, int k, const double* V, double* AV, double* BV, double* SV);
+
+// Algorithmic flops of one product pass over k vectors at the given order.
+double sigma_flops(const Context& c, int order, int k);
+
+}  // namespace ppw

@@ -1,0 +1,285 @@
+// Batched strided GEMM on CDNA4 matrix cores (FP64 and FP32 MFMA).
+//
+// Every contraction of the density-fitted sigma product (first-order Coulomb and
+// exchange terms, the second-order amplitude strips and the amplitude-weighted
+// ladder/ring contractions) and of the subspace solver is expressed as one
+// GemmDesc; this file owns the only dense-contraction kernel of the library.
+//
+// Design (gfx950):
+//  * 256 threads = 4 wave64, arranged 2x2; each wave owns a (BM/2)x(BN/2) block of
+//    C made of 16x16 MFMA tiles (v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32).
+//  * A and B tiles (BK deep) are staged through LDS in k-major layout
+//    ([BK][BM+pad]) so that one MFMA operand fragment is a 16-lane contiguous
+//    read; two LDS buffers and a register prefetch of the next tile overlap global
+//    loads with matrix-core work (one barrier per BK step).
+//  * Workgroup ids are remapped so that the tiles an XCD runs are contiguous in a
+//    grouped (row-band) order: tiles sharing A rows or B columns hit the same L2.
+//  * Split-K (over the flattened outer x inner reduction) writes per-split partial
+//    tiles to a caller workspace; a second kernel sums them in split order, so the
+//    result is deterministic and independent of the launch shape of other work.
+#include "common.h"
+
+#include <algorithm>
+
+namespace ppw {
+namespace {
+
+template <typename T>
+struct Mfma;
+
+// Operand layout (both types): lane l supplies A[l%16][l/16] and B[l/16][l%16].
+// Result layout (measured on gfx950): FP64 lane l, register r holds D[l/16 + 4r][l%16];
+// FP32 lane l, register r holds D[4(l/16) + r][l%16].
+template <>
+struct Mfma<double> {
+  typedef double acc_t __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+
+template <>
+struct Mfma<float> {
+  typedef float acc_t __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ void tile_coords(int bid, int tiles_m, int tiles_n, int& tm, int& tn) {
+  const int ntiles = tiles_m * tiles_n;
+  // XCD-aware remap: hardware dispatches consecutive ids round-robin over 8 XCDs.
+  int id = bid;
+  const int per = ntiles / 8;
+  if (per > 0 && bid < per * 8) id = (bid % 8) * per + bid / 8;
+  // grouped ordering: bands of GROUP tile-rows walked column by column
+  constexpr int GROUP = 8;
+  const int in_group = GROUP * tiles_n;
+  const int g = id / in_group;
+  const int first_m = g * GROUP;
+  const int gsize = min(tiles_m - first_m, GROUP);
+  const int r = id % in_group;
+  tm = first_m + r % gsize;
+  tn = r / gsize;
+}
+
+template <typename T, int BM, int BN, int BK>
+__global__ __launch_bounds__(kThreads) void gemm_kernel(GemmDesc d, T alpha, const T* __restrict__ A,
+                                                        const T* __restrict__ B, T beta, T* __restrict__ C,
+                                                        T* __restrict__ W, int splitk) {
+  using acc_t = typename Mfma<T>::acc_t;
+  constexpr int PAD = 16 / sizeof(T);
+  constexpr int WTM = BM / 2, WTN = BN / 2;
+  constexpr int TM = WTM / 16, TN = WTN / 16;
+  constexpr int LA = BM * BK / kThreads, LB = BN * BK / kThreads;
+  static_assert(LA * kThreads == BM * BK && LB * kThreads == BN * BK, "tile/thread mismatch");
+  __shared__ T As[2][BK][BM + PAD];
+  __shared__ T Bs[2][BK][BN + PAD];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  const int tiles_m = (d.M + BM - 1) / BM;
+  const int tiles_n = (d.N + BN - 1) / BN;
+  int tm, tn;
+  tile_coords(blockIdx.x, tiles_m, tiles_n, tm, tn);
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int batch = blockIdx.y;
+  const int b1 = batch / d.nb2, b2 = batch % d.nb2;
+  const int split = blockIdx.z;
+
+  const T* Ab = A + b1 * d.sA1 + b2 * d.sA2;
+  const T* Bb = B + b1 * d.sB1 + b2 * d.sB2;
+  const int nkt = (d.K + BK - 1) / BK;
+  const long total = (long)d.KB * nkt;
+  const long chunk = (total + splitk - 1) / splitk;
+  const long it0 = (long)split * chunk;
+  const long it1 = min(total, it0 + chunk);
+
+  acc_t acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+
+  T ra[LA], rb[LB];
+  const bool tA = d.transA != 0, tB = d.transB != 0;
+
+  auto load = [&](long it) {
+    const int kb = (int)(it / nkt);
+    const int k0 = (int)(it % nkt) * BK;
+    const T* Ak = Ab + kb * d.sAk;
+    const T* Bk = Bb + kb * d.sBk;
+#pragma unroll
+    for (int i = 0; i < LA; ++i) {
+      const int e = i * kThreads + tid;
+      const int m = tA ? (e % BM) : (e / BK);
+      const int k = tA ? (e / BM) : (e % BK);
+      const int gm = m0 + m, gk = k0 + k;
+      T v = T(0);
+      if (gm < d.M && gk < d.K) v = tA ? Ak[(long)gk * d.lda + gm] : Ak[(long)gm * d.lda + gk];
+      ra[i] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < LB; ++i) {
+      const int e = i * kThreads + tid;
+      const int n = tB ? (e / BK) : (e % BN);
+      const int k = tB ? (e % BK) : (e / BN);
+      const int gn = n0 + n, gk = k0 + k;
+      T v = T(0);
+      if (gn < d.N && gk < d.K) v = tB ? Bk[(long)gn * d.ldb + gk] : Bk[(long)gk * d.ldb + gn];
+      rb[i] = v;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < LA; ++i) {
+      const int e = i * kThreads + tid;
+      const int m = tA ? (e % BM) : (e / BK);
+      const int k = tA ? (e / BM) : (e % BK);
+      As[buf][k][m] = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < LB; ++i) {
+      const int e = i * kThreads + tid;
+      const int n = tB ? (e / BK) : (e % BN);
+      const int k = tB ? (e % BK) : (e / BN);
+      Bs[buf][k][n] = rb[i];
+    }
+  };
+
+  if (it0 < it1) {
+    load(it0);
+    store(0);
+    __syncthreads();
+    int buf = 0;
+    for (long it = it0; it < it1; ++it) {
+      const bool more = it + 1 < it1;
+      if (more) load(it + 1);
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        const int kr = kk + (lane >> 4);
+        T a[TM], b[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) a[i] = As[buf][kr][wm * WTM + i * 16 + (lane & 15)];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) b[j] = Bs[buf][kr][wn * WTN + j * 16 + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j) acc[i][j] = Mfma<T>::mma(a[i], b[j], acc[i][j]);
+      }
+      if (more) store(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+  }
+
+  const long nbatch = (long)d.nb1 * d.nb2;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * WTM + i * 16 + Mfma<T>::row(lane, r);
+        const int col = n0 + wn * WTN + j * 16 + (lane & 15);
+        if (row < d.M && col < d.N) {
+          const T v = acc[i][j][r];
+          if (W) {
+            W[((long)split * nbatch + batch) * ((long)d.M * d.N) + (long)row * d.N + col] = v;
+          } else {
+            T* cp = C + b1 * d.sC1 + b2 * d.sC2 + (long)row * d.ldc + col;
+            T out = alpha * v;
+            if (beta != T(0)) out += beta * (*cp);
+            *cp = out;
+          }
+        }
+      }
+}
+
+template <typename T>
+__global__ void splitk_reduce_kernel(GemmDesc d, T alpha, T beta, const T* __restrict__ W, T* __restrict__ C,
+                                     int splitk) {
+  const long per = (long)d.M * d.N;
+  const long nbatch = (long)d.nb1 * d.nb2;
+  const long total = per * nbatch;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+    const long batch = idx / per;
+    const long rc = idx % per;
+    const int row = (int)(rc / d.N), col = (int)(rc % d.N);
+    T s = T(0);
+    for (int k = 0; k < splitk; ++k) s += W[((long)k * nbatch + batch) * per + rc];
+    const int b1 = (int)(batch / d.nb2), b2 = (int)(batch % d.nb2);
+    T* cp = C + b1 * d.sC1 + b2 * d.sC2 + (long)row * d.ldc + col;
+    T out = alpha * s;
+    if (beta != T(0)) out += beta * (*cp);
+    *cp = out;
+  }
+}
+
+template <typename T, int BM, int BN, int BK>
+void launch(const GemmDesc& d, T alpha, const T* A, const T* B, T beta, T* C, hipStream_t s, Workspace ws) {
+  const int tiles_m = (d.M + BM - 1) / BM, tiles_n = (d.N + BN - 1) / BN;
+  const long nbatch = (long)d.nb1 * d.nb2;
+  if (nbatch > 65535) throw InvalidArg("gemm: batch count exceeds 65535");
+  const long ntiles = (long)tiles_m * tiles_n;
+  const int nkt = (d.K + BK - 1) / BK;
+  const long total = (long)d.KB * nkt;
+  // split the reduction when the grid is too small to fill 256 CUs
+  int splitk = 1;
+  const long wgs = ntiles * nbatch;
+  if (wgs < 512 && total >= 8) {
+    long want = (1024 + wgs - 1) / wgs;
+    want = std::min<long>(want, total / 4);
+    const size_t per = (size_t)d.M * d.N * nbatch * sizeof(T);
+    if (per > 0) want = std::min<long>(want, (long)(ws.bytes / per));
+    want = std::min<long>(want, 256);
+    if (want >= 2) splitk = (int)want;
+  }
+  dim3 grid((unsigned)ntiles, (unsigned)nbatch, (unsigned)splitk);
+  if (splitk == 1) {
+    gemm_kernel<T, BM, BN, BK><<<grid, kThreads, 0, s>>>(d, alpha, A, B, beta, C, nullptr, 1);
+    PPW_LAUNCH_CHECK();
+  } else {
+    T* W = static_cast<T*>(ws.ptr);
+    gemm_kernel<T, BM, BN, BK><<<grid, kThreads, 0, s>>>(d, alpha, A, B, beta, C, W, splitk);
+    PPW_LAUNCH_CHECK();
+    const long n = (long)d.M * d.N * nbatch;
+    const int blocks = (int)std::min<long>((n + 255) / 256, 8192);
+    splitk_reduce_kernel<T><<<blocks, 256, 0, s>>>(d, alpha, beta, W, C, splitk);
+    PPW_LAUNCH_CHECK();
+  }
+}
+
+template <typename T>
+void gemm_dispatch(const GemmDesc& d, T alpha, const T* A, const T* B, T beta, T* C, hipStream_t s,
+                   Workspace ws) {
+  if (d.M <= 0 || d.N <= 0 || d.nb1 <= 0 || d.nb2 <= 0) return;
+  if (d.K <= 0 || d.KB <= 0) throw InvalidArg("gemm: empty reduction");
+  const bool big = d.M >= 96 && d.N >= 96;
+  if (big)
+    launch<T, 128, 128, 16>(d, alpha, A, B, beta, C, s, ws);
+  else
+    launch<T, 64, 64, 16>(d, alpha, A, B, beta, C, s, ws);
+}
+
+}  // namespace
+
+void gemm_f64(const GemmDesc& d, double alpha, const double* A, const double* B, double beta, double* C,
+              hipStream_t s, Workspace ws) {
+  gemm_dispatch<double>(d, alpha, A, B, beta, C, s, ws);
+}
+
+void gemm_f32(const GemmDesc& d, float alpha, const float* A, const float* B, float beta, float* C,
+              hipStream_t s, Workspace ws) {
+  gemm_dispatch<float>(d, alpha, A, B, beta, C, s, ws);
+}
+
+}  // namespace ppw

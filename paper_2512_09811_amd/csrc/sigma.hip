@@ -1,0 +1,444 @@
+// Setup of a system and the matrix-free product of the response matrix.
+//
+// Working equations (closed-shell singlet, density-fitted; index ia = i*v + a),
+// for a block V of k particle-hole vectors:
+//
+//   first order   A V = Delta V + 2 J(V) - K_A(V),   B V = 2 J(V) - K_B(V)
+//                 J(V)_ia  = sum_P B_P,ia sum_jb B_P,jb V_jb
+//                 K_A(V)   = sum_P B^oo_P V B^vv_P
+//                 K_B(V)   = sum_P B^ov_P V^T B^ov_P
+//   second order  S V     += -Go V - V Gv
+//                 A V     += -V Ev + e_i (V Gv) - e_a (Go V) - Eo V
+//                 B V     += sum_P (H_P B^vv_P - B^oo_P H_P)
+//                            - sum_P (B^ov_P V^T Lam_P + Lam_P V^T B^ov_P)
+//                 G_P = V B^vv_P - B^oo_P V,  H_P,ic = sum_jd tau_ij^cd G_P,jd
+//
+// with tau_ij^ab = 2 t_ij^ab - t_ij^ba, t_ij^ab = (ia|jb)/(e_i + e_j - e_a - e_b),
+// Gv/Ev/Go/Eo the (energy-weighted) MP2 densities and Lam_P,ia = sum_kc tau_ik^ac B_P,kc.
+// These are the closed forms of the second-order expectation values of the
+// second-order section (metric, A and B over the MP2 ground state), written
+// through the DF factors so that no four-index quantity except amplitude strips
+// tau_i (v x N per occupied i) is ever formed.  The dominant contraction is
+// H = tau G (o^2 v^2 naux k multiply-adds); with stored amplitudes it is one
+// N x N x (naux k) GEMM, otherwise one GEMM per strip batch after the strip is
+// rebuilt from B^ov (K = naux) and the denominators.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "context.h"
+#include "kernels.h"
+
+namespace ppw {
+
+Context::~Context() {
+  arena.release();
+  if (own_stream && stream) (void)hipStreamDestroy(stream);
+}
+
+namespace {
+
+GemmDesc gd(int M, int N, int K, int transA, long lda, int transB, long ldb, long ldc) {
+  GemmDesc d;
+  d.M = M;
+  d.N = N;
+  d.K = K;
+  d.transA = transA;
+  d.lda = lda;
+  d.transB = transB;
+  d.ldb = ldb;
+  d.ldc = ldc;
+  return d;
+}
+
+void copy_in(double* dst, const double* src, size_t n, bool dev, hipStream_t s) {
+  PPW_HIP(hipMemcpyAsync(dst, src, n * sizeof(double), dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+}
+
+void ensure_ws(Context& c, size_t bytes) {
+  if (bytes <= c.ws_bytes) return;
+  if (c.ws.ptr) c.arena.free(c.ws.ptr);
+  c.ws.ptr = c.arena.alloc<char>(bytes, "split-K workspace");
+  c.ws.bytes = bytes;
+  c.ws_bytes = bytes;
+}
+
+// rows per amplitude strip batch that fit 'bytes' with 'arrays' strip-sized arrays
+int strip_rows_for(const Context& c, size_t bytes, int arrays) {
+  const size_t per_row = (size_t)c.v * c.N * sizeof(double) * arrays;
+  int ib = (int)std::max<size_t>(1, bytes / std::max<size_t>(per_row, 1));
+  return std::min(ib, c.o);
+}
+
+}  // namespace
+
+double sigma_flops(const Context& c, int order, int k) {
+  if (order <= 0) return 0.0;
+  const double o = c.o, v = c.v, X = c.naux, N = (double)c.N, K = k;
+  double f = 0.0;
+  f += 2.0 * X * N * K * 2.0;                  // J (two GEMMs)
+  f += 2.0 * K * X * o * v * v;                // V B^vv_P for all P
+  f += 2.0 * K * X * o * o * v;                // sum_P B^oo_P (.)   (K_A)
+  const double ns = order >= 2 ? 2.0 : 1.0;
+  f += 2.0 * K * o * v * ns * X * o;           // V^T [B^ov; Lam]
+  f += 2.0 * K * o * ns * X * o * v;           // ring / K_B output
+  if (order >= 2) {
+    f += 2.0 * K * X * o * o * v;              // - B^oo_P V   (G)
+    f += 2.0 * N * N * K * X;                  // H = tau G    (dominant)
+    f += 2.0 * K * X * o * v * v;              // H B^vv
+    f += 2.0 * K * X * o * o * v;              // B^oo H
+    f += 2.0 * K * o * v * v * 2.0;            // V Gv, V Ev
+    f += 2.0 * K * o * o * v * 2.0;            // Go V, Eo V
+  }
+  return f;
+}
+
+Context* setup_context(const SetupParams& p) {
+  if (p.o < 1 || p.v < 1 || p.naux < 1) throw InvalidArg("n_occ, n_vir and n_aux must be positive");
+  if (p.order < 0 || p.order > 2) throw InvalidArg("order must be 0, 1 or 2");
+  if (!p.eps || !p.Boo || !p.Bov || !p.Bvv) throw InvalidArg("eps, B_oo, B_ov and B_vv are required");
+  if ((long)p.o * p.v > 2147483647L / 2) throw InvalidArg("particle-hole dimension too large");
+  auto* c = new Context();
+  try {
+    c->o = p.o;
+    c->v = p.v;
+    c->naux = p.naux;
+    c->order = p.order;
+    c->N = (long)p.o * p.v;
+    c->device = p.device;
+    PPW_HIP(hipSetDevice(p.device));
+    if (p.stream) {
+      c->stream = p.stream;
+    } else {
+      PPW_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+      c->own_stream = true;
+    }
+    size_t freeb = 0, totalb = 0;
+    PPW_HIP(hipMemGetInfo(&freeb, &totalb));
+    c->arena.set_budget(p.budget ? p.budget : (size_t)(0.9 * (double)freeb));
+    hipStream_t s = c->stream;
+    const int o = p.o, v = p.v, X = p.naux;
+    const long N = c->N;
+
+    c->eps_o = c->arena.alloc<double>(o, "eps_o");
+    c->eps_v = c->arena.alloc<double>(v, "eps_v");
+    c->Boo = c->arena.alloc<double>((size_t)X * o * o, "B_oo");
+    c->Bvv = c->arena.alloc<double>((size_t)X * v * v, "B_vv");
+    c->ns = p.order >= 2 ? 2 : 1;
+    c->BovLam = c->arena.alloc<double>((size_t)c->ns * X * N, "B_ov");
+    c->Bov = c->BovLam;
+    if (p.order >= 2) c->Lam = c->BovLam + (size_t)X * N;
+    copy_in(c->eps_o, p.eps, o, p.device_ptrs, s);
+    copy_in(c->eps_v, p.eps + o, v, p.device_ptrs, s);
+    copy_in(c->Boo, p.Boo, (size_t)X * o * o, p.device_ptrs, s);
+    copy_in(c->Bov, p.Bov, (size_t)X * N, p.device_ptrs, s);
+    copy_in(c->Bvv, p.Bvv, (size_t)X * v * v, p.device_ptrs, s);
+    if (p.dip) {
+      c->dip = c->arena.alloc<double>((size_t)3 * N, "dip");
+      copy_in(c->dip, p.dip, (size_t)3 * N, p.device_ptrs, s);
+    }
+    // layouts
+    c->Boo_t = c->arena.alloc<double>((size_t)o * o * X, "B_oo [i][j][P]");
+    const int perm[3] = {1, 2, 0};
+    permute3(c->Boo, c->Boo_t, X, o, o, perm, s);
+    ensure_ws(*c, std::max<size_t>((size_t)64 << 20, (size_t)X * 1024 * sizeof(double)));
+
+    double* coul = c->arena.alloc<double>(N, "diag tmp");
+    double* exch = c->arena.alloc<double>(N, "diag tmp");
+    diag_integrals(c->Bov, c->Boo, c->Bvv, o, v, X, coul, exch, s);
+    c->dA = c->arena.alloc<double>(N, "diag A");
+    c->dB = c->arena.alloc<double>(N, "diag B");
+    c->dS = c->arena.alloc<double>(N, "diag S");
+
+    if (p.order >= 2) {
+      c->Gv = c->arena.alloc<double>((size_t)v * v, "Gv");
+      c->Ev = c->arena.alloc<double>((size_t)v * v, "Ev");
+      c->Go = c->arena.alloc<double>((size_t)o * o, "Go");
+      c->Eo = c->arena.alloc<double>((size_t)o * o, "Eo");
+      PPW_HIP(hipMemsetAsync(c->Gv, 0, sizeof(double) * v * v, s));
+      PPW_HIP(hipMemsetAsync(c->Ev, 0, sizeof(double) * v * v, s));
+      PPW_HIP(hipMemsetAsync(c->Go, 0, sizeof(double) * o * o, s));
+      PPW_HIP(hipMemsetAsync(c->Eo, 0, sizeof(double) * o * o, s));
+      // amplitudes: store them all when requested / when they fit comfortably
+      const size_t tau_bytes = (size_t)N * N * sizeof(double);
+      bool store = p.store_amplitudes == 1;
+      if (p.store_amplitudes < 0)
+        store = c->arena.used() + 6 * tau_bytes < c->arena.budget() / 2;
+      if (store) c->tau = c->arena.alloc<double>((size_t)N * N, "amplitudes tau");
+      // strip batch size for the setup (S, tau, t, tEv, tEo = 5 arrays)
+      const size_t room = c->arena.budget() > c->arena.used() ? c->arena.budget() - c->arena.used() : 0;
+      int ib = p.strip_rows > 0 ? std::min(p.strip_rows, o) : strip_rows_for(*c, room / 3, store ? 4 : 5);
+      c->strip_rows = ib;
+      const size_t strip = (size_t)ib * v * N;
+      double* S = c->arena.alloc<double>(strip, "strip S");
+      double* tauS = store ? nullptr : c->arena.alloc<double>(strip, "strip tau");
+      double* t = c->arena.alloc<double>(strip, "strip t");
+      double* tEv = c->arena.alloc<double>(strip, "strip tEv");
+      double* tEo = c->arena.alloc<double>(strip, "strip tEo");
+      const long nblk = tau_blocks(o, v, ib);
+      double* partial = c->arena.alloc<double>((size_t)nblk * ((o + ib - 1) / ib), "energy partials");
+      long pofs = 0;
+      for (int k0 = 0; k0 < o; k0 += ib) {
+        const int nb = std::min(ib, o - k0);
+        double* tau_b = store ? c->tau + (size_t)k0 * v * N : tauS;
+        // S[(k,x)][(l,y)] = sum_P B_P,kx B_P,ly
+        GemmDesc d = gd(nb * v, (int)N, X, 1, N, 0, N, N);
+        gemm_f64(d, 1.0, c->Bov + (size_t)k0 * v, c->Bov, 0.0, S, s, c->ws);
+        tau_strip(S, o, v, k0, nb, c->eps_o, c->eps_v, tau_b, t, tEv, tEo, partial + pofs, s);
+        pofs += tau_blocks(o, v, nb);
+        // Gv[a][b] += sum_k sum_(l,y) tau[(k,a)][(l,y)] t[(k,b)][(l,y)]
+        GemmDesc g = gd(v, v, (int)N, 0, N, 1, N, v);
+        g.KB = nb;
+        g.sAk = (long)v * N;
+        g.sBk = (long)v * N;
+        gemm_f64(g, 1.0, tau_b, t, 1.0, c->Gv, s, c->ws);
+        gemm_f64(g, 1.0, tau_b, tEv, 1.0, c->Ev, s, c->ws);
+        // Go[i][j] += sum_(k,x) sum_y tau[(k,x)][(i,y)] t[(k,x)][(j,y)]
+        GemmDesc h = gd(o, o, v, 0, v, 1, v, o);
+        h.KB = nb * v;
+        h.sAk = N;
+        h.sBk = N;
+        gemm_f64(h, 1.0, tau_b, t, 1.0, c->Go, s, c->ws);
+        gemm_f64(h, 1.0, tau_b, tEo, 1.0, c->Eo, s, c->ws);
+        // Lam[P][(i,a)] = sum_(l,y) Bov[P][(l,y)] tau[(i,a)][(l,y)]   (i in batch)
+        GemmDesc l = gd(X, nb * v, (int)N, 0, N, 1, N, N);
+        gemm_f64(l, 1.0, c->Bov, tau_b, 0.0, c->Lam + (size_t)k0 * v, s, c->ws);
+      }
+      double* e2 = c->arena.alloc<double>(1, "emp2");
+      sum_reduce(partial, pofs, e2, s);
+      PPW_HIP(hipMemcpyAsync(&c->emp2, e2, sizeof(double), hipMemcpyDeviceToHost, s));
+      PPW_HIP(hipStreamSynchronize(s));
+      c->arena.free(partial);
+      c->arena.free(tEo);
+      c->arena.free(tEv);
+      c->arena.free(t);
+      if (tauS) c->arena.free(tauS);
+      c->arena.free(S);
+      c->arena.free(e2);
+    }
+    diag_assemble(o, v, p.order, c->eps_o, c->eps_v, coul, exch, c->Gv, c->Ev, c->Go, c->Eo, c->dA, c->dB, c->dS,
+                  s);
+    c->R = c->arena.alloc<double>((size_t)o * c->ns * X * v, "ring operand");
+    build_ring_operand(c->Bov, c->Lam, o, v, X, c->R, s);
+    PPW_HIP(hipStreamSynchronize(s));
+    c->arena.free(exch);
+    c->arena.free(coul);
+    if (c->strip_rows == 0) c->strip_rows = o;
+  } catch (...) {
+    delete c;
+    throw;
+  }
+  return c;
+}
+
+namespace {
+
+void grow_workspace(Context& c, int k) {
+  if (k <= c.kcap) return;
+  const int o = c.o, v = c.v, X = c.naux;
+  const long N = c.N;
+  auto re = [&](double*& p, size_t n, const char* w) {
+    if (p) c.arena.free(p);
+    p = c.arena.alloc<double>(n, w);
+  };
+  re(c.w_c, (size_t)X * k, "ws c");
+  re(c.w_J, (size_t)k * N, "ws J");
+  re(c.w_G, (size_t)k * X * N, "ws G");
+  re(c.w_U, (size_t)k * o * c.ns * X * o, "ws U");
+  re(c.w_P, (size_t)4 * k * N, "ws P");
+  if (c.order >= 2) {
+    const int ib = c.tau ? o : c.strip_rows;
+    re(c.w_H, (size_t)ib * v * k * X, "ws H");
+    if (!c.tau) {
+      re(c.w_S, (size_t)c.strip_rows * v * N, "ws strip S");
+      re(c.w_tau, (size_t)c.strip_rows * v * N, "ws strip tau");
+    }
+  }
+  c.kcap = k;
+}
+
+struct EventTimer {
+  hipEvent_t a = nullptr, b = nullptr;
+  hipStream_t s;
+  explicit EventTimer(hipStream_t s_) : s(s_) {
+    PPW_HIP(hipEventCreate(&a));
+    PPW_HIP(hipEventCreate(&b));
+    PPW_HIP(hipEventRecord(a, s));
+  }
+  float stop() {
+    PPW_HIP(hipEventRecord(b, s));
+    PPW_HIP(hipEventSynchronize(b));
+    float ms = 0.f;
+    PPW_HIP(hipEventElapsedTime(&ms, a, b));
+    return ms;
+  }
+  ~EventTimer() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
+}  // namespace
+
+void sigma_core(Context& c, int order, int k, const double* V, double* AV, double* BV, double* SV) {
+  if (order > c.order) throw InvalidArg("requested order exceeds the setup order");
+  if (k <= 0) return;
+  hipStream_t s = c.stream;
+  const int o = c.o, v = c.v, X = c.naux;
+  const long N = c.N;
+  if (order == 0) {
+    sigma_assemble(o, v, k, 0, c.eps_o, c.eps_v, V, nullptr, nullptr, nullptr, nullptr, nullptr, AV, BV, SV, s);
+    return;
+  }
+  grow_workspace(c, k);
+  EventTimer timer(s);
+  double* cP = c.w_c;
+  double* J = c.w_J;
+  double* G = c.w_G;
+  double* U = c.w_U;
+  double* P1 = c.w_P;
+  double* P2 = P1 + (size_t)k * N;
+  double* P3 = P2 + (size_t)k * N;
+  double* P4 = P3 + (size_t)k * N;
+
+  // J: c[P][q] = sum_ia Bov[P][ia] V[q][ia];  J[q][ia] = sum_P c[P][q] Bov[P][ia]
+  gemm_f64(gd(X, k, (int)N, 0, N, 1, N, k), 1.0, c.Bov, V, 0.0, cP, s, c.ws);
+  gemm_f64(gd(k, (int)N, X, 1, k, 0, N, N), 1.0, cP, c.Bov, 0.0, J, s, c.ws);
+
+  // G1[q][P][j][d] = sum_b V[q][j][b] Bvv[P][b][d]
+  {
+    GemmDesc d = gd(o, v, v, 0, v, 0, v, v);
+    d.nb1 = k;
+    d.nb2 = X;
+    d.sA1 = N;
+    d.sA2 = 0;
+    d.sB1 = 0;
+    d.sB2 = (long)v * v;
+    d.sC1 = (long)X * N;
+    d.sC2 = N;
+    gemm_f64(d, 1.0, V, c.Bvv, 0.0, G, s, c.ws);
+  }
+  // AV = -K_A(V) = -sum_P Boo_P G1_P
+  {
+    GemmDesc d = gd(o, v, o, 0, o, 0, v, v);
+    d.KB = X;
+    d.sAk = (long)o * o;
+    d.sBk = N;
+    d.nb1 = k;
+    d.sB1 = (long)X * N;
+    d.sC1 = N;
+    gemm_f64(d, -1.0, c.Boo, G, 0.0, AV, s, c.ws);
+  }
+  // U[(q,j)][(s,P,i)] = sum_b V[(q,j)][b] BovLam[(s,P,i)][b]
+  const int ns = order >= 2 ? 2 : 1;
+  const double* Rop = c.R;
+  {
+    const long Ucols = (long)ns * X * o;
+    gemm_f64(gd(k * o, (int)Ucols, v, 0, v, 1, v, Ucols), 1.0, V, c.BovLam, 0.0, U, s, c.ws);
+    // BV = -sum_(j,s,P) U[q][(j,s,P)][i] R[(j,s,P)][a]
+    if (ns == c.ns) {
+      GemmDesc d = gd(o, v, o * ns * X, 1, o, 0, v, v);
+      d.nb1 = k;
+      d.sA1 = (long)o * Ucols;
+      d.sC1 = N;
+      gemm_f64(d, -1.0, U, Rop, 0.0, BV, s, c.ws);
+    } else {
+      // order-1 product on an order-2 handle: K_B(V) = sum_(j,P) U[q][(j,P)][i] Bov[P][j][a]
+      // with R[j][1][P][a] = Bov[P][j][a]: outer loop over j (stride 2 X v), inner P.
+      GemmDesc d = gd(o, v, X, 1, o, 0, v, v);
+      d.KB = o;
+      d.sAk = (long)X * o;
+      d.sBk = (long)c.ns * X * v;
+      d.nb1 = k;
+      d.sA1 = (long)o * Ucols;
+      d.sC1 = N;
+      gemm_f64(d, -1.0, U, Rop + (size_t)X * v, 0.0, BV, s, c.ws);
+    }
+  }
+
+  if (order >= 2) {
+    // G_P = V Bvv_P - Boo_P V  (in place on G1)
+    {
+      GemmDesc d = gd(o, v, o, 0, o, 0, v, v);
+      d.nb1 = k;
+      d.nb2 = X;
+      d.sA1 = 0;
+      d.sA2 = (long)o * o;
+      d.sB1 = N;
+      d.sB2 = 0;
+      d.sC1 = (long)X * N;
+      d.sC2 = N;
+      gemm_f64(d, -1.0, c.Boo, V, 1.0, G, s, c.ws);
+    }
+    const long kX = (long)k * X;
+    auto outputs = [&](const double* H, int i0, int ib) {
+      // BV[q][i][a] += sum_(c,P) H[(i,c)][(q,P)] Bvv[P][c][a]    for rows i0..i0+ib-1
+      {
+        GemmDesc d = gd(ib, v, X, 0, (long)v * kX, 0, (long)v * v, v);
+        d.KB = v;
+        d.sAk = kX;
+        d.sBk = v;
+        d.nb1 = k;
+        d.sA1 = X;
+        d.sC1 = N;
+        gemm_f64(d, 1.0, H, c.Bvv, 1.0, BV + (size_t)i0 * v, s, c.ws);
+      }
+      // BV[q][i][a] -= sum_(kk,P) Boo[P][i][kk] H[(kk,a)][(q,P)]   for kk in i0..i0+ib-1
+      {
+        GemmDesc d = gd(o, v, X, 0, (long)o * X, 1, kX, v);
+        d.KB = ib;
+        d.sAk = X;
+        d.sBk = (long)v * kX;
+        d.nb1 = k;
+        d.sB1 = X;
+        d.sC1 = N;
+        gemm_f64(d, -1.0, c.Boo_t + (size_t)i0 * X, H, 1.0, BV, s, c.ws);
+      }
+    };
+    EventTimer th(s);
+    double hflops = 0.0;
+    if (c.tau) {
+      // H[(i,c)][(q,P)] = sum_(j,d) tau[(i,c)][(j,d)] G[(q,P)][(j,d)]
+      GemmDesc d = gd((int)N, (int)kX, (int)N, 0, N, 1, N, kX);
+      gemm_f64(d, 1.0, c.tau, G, 0.0, c.w_H, s, c.ws);
+      hflops += gemm_flops(d);
+      c.stats.hhat_launches += 1;
+      outputs(c.w_H, 0, o);
+    } else {
+      const int ib = c.strip_rows;
+      for (int i0 = 0; i0 < o; i0 += ib) {
+        const int nb = std::min(ib, o - i0);
+        gemm_f64(gd(nb * v, (int)N, X, 1, N, 0, N, N), 1.0, c.Bov + (size_t)i0 * v, c.Bov, 0.0, c.w_S, s, c.ws);
+        tau_strip(c.w_S, o, v, i0, nb, c.eps_o, c.eps_v, c.w_tau, nullptr, nullptr, nullptr, nullptr, s);
+        GemmDesc d = gd(nb * v, (int)kX, (int)N, 0, N, 1, N, kX);
+        gemm_f64(d, 1.0, c.w_tau, G, 0.0, c.w_H, s, c.ws);
+        hflops += gemm_flops(d);
+        c.stats.hhat_launches += 1;
+        outputs(c.w_H, i0, nb);
+      }
+    }
+    c.stats.hhat_seconds += th.stop() * 1e-3;
+    c.stats.hhat_flops += hflops;
+    // delta-type terms: P1 = V Gv, P2 = V Ev, P3 = Go V, P4 = Eo V
+    gemm_f64(gd(k * o, v, v, 0, v, 0, v, v), 1.0, V, c.Gv, 0.0, P1, s, c.ws);
+    gemm_f64(gd(k * o, v, v, 0, v, 0, v, v), 1.0, V, c.Ev, 0.0, P2, s, c.ws);
+    {
+      GemmDesc d = gd(o, v, o, 0, o, 0, v, v);
+      d.nb1 = k;
+      d.sB1 = N;
+      d.sC1 = N;
+      gemm_f64(d, 1.0, c.Go, V, 0.0, P3, s, c.ws);
+      gemm_f64(d, 1.0, c.Eo, V, 0.0, P4, s, c.ws);
+    }
+  }
+  sigma_assemble(o, v, k, order, c.eps_o, c.eps_v, V, J, P1, P2, P3, P4, AV, BV, SV, s);
+  c.stats.seconds += timer.stop() * 1e-3;
+  c.stats.flops += sigma_flops(c, order, k);
+  c.stats.vectors += k;
+}
+
+void sigma_core_f32(Context&, int, int, const double*, double*, double*, double*) {
+  throw NotSupported("FP32 product path not built");
+}
+
+}  // namespace ppw

@@ -1,0 +1,35 @@
+// Frequency-window solver and the small dense FP64 kernels it uses.
+#pragma once
+
+#include "../../include/ppwin.h"
+#include "context.h"
+
+namespace ppw {
+
+struct SolveOptions {
+  int precision = 0;      // 0 FP64 products, 1 FP32 products for the subspace
+  double tol = 1e-9;
+  int block = 0;
+  int krylov_steps = 2;
+  int max_basis = 400;
+  int max_cycles = 200;
+  double d_clamp = 1e-4;
+  unsigned long long seed = 0;
+};
+
+// Roots of M z = omega Sigma z nearest omega0 (positive branch).  Host outputs.
+// Throws NotConverged after writing all outputs when max_cycles is reached.
+void window_solve(Context& c, const SolveOptions& opt, double omega0, int n_roots, double* energies,
+                  double* vectors, double* osc, pp_solve_info* info);
+
+// One-workgroup FP64 kernels on small n x n row-major matrices (n <= 512).
+//  small_syev: A symmetric -> w ascending, Z[r*n + c] = component r of vector c.
+//  scratch: 2 n^2 doubles (null: allocated and freed internally).
+void small_syev(int n, const double* A, double* w, double* Z, hipStream_t s, double* scratch = nullptr);
+//  small_cholesky: lower factor L (zeros above the diagonal); *info (device int,
+//  may be null) = 0 on success, j+1 if the leading minor j is not positive.
+void small_cholesky(int n, const double* A, double* L, int* info, hipStream_t s);
+//  small_trinv: X = L^-1 for lower-triangular L.
+void small_trinv(int n, const double* L, double* X, hipStream_t s);
+
+}  // namespace ppw

@@ -1,0 +1,107 @@
+"""GPU checks of the library's building blocks against plain references.
+
+GEMM (every layout, batches, outer reduction, split-K, ragged edges) against a
+float64 numpy product; the one-workgroup eigensolver and Cholesky against
+LAPACK.  All calls go through the C ABI test hooks.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2512_09811_amd import binding
+    binding.lib()
+    assert torch.cuda.is_available()
+    return binding
+
+
+def _ref_gemm(A, Bm, M, N, K, KB, nb, tA, lda, sA, sAk, tB, ldb, sB, sBk):
+    out = np.zeros((nb, M, N))
+    for b in range(nb):
+        for kb in range(KB):
+            a0 = b * sA + kb * sAk
+            b0 = b * sB + kb * sBk
+            if tA:
+                Am = np.array([[A[a0 + k * lda + m] for k in range(K)] for m in range(M)])
+            else:
+                Am = np.array([[A[a0 + m * lda + k] for k in range(K)] for m in range(M)])
+            if tB:
+                Bk = np.array([[Bm[b0 + n * ldb + k] for n in range(N)] for k in range(K)])
+            else:
+                Bk = np.array([[Bm[b0 + k * ldb + n] for n in range(N)] for k in range(K)])
+            out[b] += Am @ Bk
+    return out
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+@pytest.mark.parametrize("M,N,K,KB,nb,tA,tB", [
+    (1, 1, 1, 1, 1, 0, 0), (37, 53, 29, 1, 1, 0, 0), (37, 53, 29, 1, 1, 1, 0), (37, 53, 29, 1, 1, 0, 1),
+    (37, 53, 29, 1, 1, 1, 1), (130, 150, 70, 1, 2, 0, 1), (20, 30, 17, 3, 2, 1, 0), (3, 5, 2000, 1, 1, 0, 1),
+    (200, 7, 3000, 2, 1, 1, 1)])
+def test_gemm_layouts(B, fp32, M, N, K, KB, nb, tA, tB):
+    rng = np.random.default_rng(M * 7 + N * 13 + K + KB + nb + tA * 3 + tB * 5)
+    lda = (M if tA else K) + 3
+    ldb = (K if tB else N) + 2
+    rowsA = K if tA else M
+    rowsB = N if tB else K
+    sAk = rowsA * lda + 5
+    sBk = rowsB * ldb + 4
+    sA = KB * sAk + 7
+    sB = KB * sBk + 3
+    ldc = N + 1
+    sC = M * ldc + 2
+    A = rng.standard_normal(nb * sA + 8)
+    Bm = rng.standard_normal(nb * sB + 8)
+    C0 = rng.standard_normal(nb * sC + 8)
+    ref = _ref_gemm(A, Bm, M, N, K, KB, nb, tA, lda, sA, sAk, tB, ldb, sB, sBk)
+    dt = torch.float32 if fp32 else torch.float64
+    dA = torch.tensor(A, dtype=dt, device="cuda")
+    dB = torch.tensor(Bm, dtype=dt, device="cuda")
+    for beta, ws in ((0.0, 0), (0.5, 1 << 24)):
+        dC = torch.tensor(C0, dtype=dt, device="cuda")
+        B.gemm(dA, dB, dC, M=M, N=N, K=K, KB=KB, nbatch=nb, transA=tA, lda=lda, sA=sA, sAk=sAk, transB=tB, ldb=ldb,
+               sB=sB, sBk=sBk, ldc=ldc, sC=sC, alpha=1.5, beta=beta, ws_bytes=ws, fp32=fp32)
+        got = dC.double().cpu().numpy()
+        exp = C0.copy()
+        for b in range(nb):
+            for m in range(M):
+                exp[b * sC + m * ldc: b * sC + m * ldc + N] = 1.5 * ref[b, m] + beta * C0[b * sC + m * ldc:
+                                                                                       b * sC + m * ldc + N]
+        scale = np.sqrt(K * KB) * 3
+        tol = (2e-6 if fp32 else 1e-14) * scale
+        np.testing.assert_allclose(got, exp, rtol=(2e-5 if fp32 else 0), atol=tol)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 37, 130, 400])
+def test_small_syev(B, n):
+    rng = np.random.default_rng(n)
+    X = rng.standard_normal((n, n))
+    A = X + X.T
+    if n >= 5:
+        A[0, :] = A[:, 0] = 0.0          # a decoupled block
+        A[0, 0] = 0.5
+    w_ref = np.linalg.eigvalsh(A)
+    dA = torch.tensor(A, dtype=torch.float64, device="cuda")
+    w = torch.empty(n, dtype=torch.float64, device="cuda")
+    Z = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    B.syev(dA, w, Z)
+    w, Z = w.cpu().numpy(), Z.cpu().numpy()
+    np.testing.assert_allclose(w, w_ref, rtol=0, atol=1e-12 * max(1.0, np.abs(w_ref).max()))
+    assert np.abs(A @ Z - Z * w).max() < 1e-11 * max(1.0, np.abs(w_ref).max())
+    assert np.abs(Z.T @ Z - np.eye(n)).max() < 1e-12
+
+
+@pytest.mark.parametrize("n", [1, 4, 33, 257])
+def test_small_cholesky(B, n):
+    rng = np.random.default_rng(n + 100)
+    X = rng.standard_normal((n, n))
+    A = X @ X.T + n * np.eye(n)
+    dA = torch.tensor(A, dtype=torch.float64, device="cuda")
+    L = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    B.cholesky(dA, L)
+    np.testing.assert_allclose(L.cpu().numpy(), np.linalg.cholesky(A), rtol=0, atol=1e-12 * np.sqrt(n))
