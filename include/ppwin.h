@@ -134,6 +134,24 @@ pp_status pp_sigma(pp_handle* h, int32_t order, int32_t m, const double* X, doub
 pp_status pp_window_solve(pp_handle* h, double omega0, int32_t n_roots, double* energies, double* vectors,
                           double* osc, pp_solve_info* info);
 
+/* Cumulative device-side accounting of the handle's products (every pp_sigma
+ * and every product inside pp_window_solve), timed with HIP events on the
+ * handle's stream.  "hhat" is the dominant contraction H = tau G of the
+ * second-order B term (one GEMM per amplitude strip batch). */
+typedef struct {
+  double product_flops;     /* algorithmic flops of all products */
+  double product_seconds;   /* device time of all products */
+  int64_t product_vectors;  /* particle-hole vectors multiplied */
+  double hhat_flops;        /* algorithmic flops of the H = tau G GEMMs */
+  double hhat_seconds;      /* device time of those GEMMs (sum over launches) */
+  int64_t hhat_launches;
+} pp_stats;
+
+/* Fills *st (synchronizes the handle's stream). */
+pp_status pp_get_stats(pp_handle* h, pp_stats* st);
+/* Zeroes the accounting. */
+pp_status pp_reset_stats(pp_handle* h);
+
 /* MP2 correlation energy sum tau_ij^ab (ia|jb) found during an order-2 setup (0 otherwise). */
 double pp_mp2_energy(const pp_handle* h);
 

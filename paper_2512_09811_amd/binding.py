@@ -49,6 +49,11 @@ class pp_solve_info(C.Structure):
                 ("seconds", C.c_double), ("sigma_seconds", C.c_double), ("sigma_flops", C.c_double)]
 
 
+class pp_stats(C.Structure):
+    _fields_ = [("product_flops", C.c_double), ("product_seconds", C.c_double), ("product_vectors", C.c_int64),
+                ("hhat_flops", C.c_double), ("hhat_seconds", C.c_double), ("hhat_launches", C.c_int64)]
+
+
 _lib = None
 
 
@@ -68,6 +73,10 @@ def lib() -> C.CDLL:
         L.pp_sigma.restype = C.c_int
         L.pp_window_solve.argtypes = [vp, dbl, i32, vp, vp, vp, C.POINTER(pp_solve_info)]
         L.pp_window_solve.restype = C.c_int
+        L.pp_get_stats.argtypes = [vp, C.POINTER(pp_stats)]
+        L.pp_get_stats.restype = C.c_int
+        L.pp_reset_stats.argtypes = [vp]
+        L.pp_reset_stats.restype = C.c_int
         L.pp_mp2_energy.argtypes = [vp]
         L.pp_mp2_energy.restype = dbl
         L.pp_device_bytes.argtypes = [vp]
@@ -115,14 +124,24 @@ def _f64(a) -> np.ndarray:
 class Handle:
     """A system set up on the device (wraps pp_handle*)."""
 
-    def __init__(self, eps, B_oo, B_ov, B_vv, dip=None, order: int = 2, options: Optional[pp_options] = None, **kw):
+    def __init__(self, eps, B_oo, B_ov, B_vv, dip=None, order: int = 2, options: Optional[pp_options] = None,
+                 device_ptrs: bool = False, **kw):
         L = lib()
-        self._arrays = [_f64(eps), _f64(B_oo), _f64(B_ov), _f64(B_vv)] + ([_f64(dip)] if dip is not None else [])
-        naux, o, v = self._arrays[2].shape
-        s = pp_system(n_occ=o, n_vir=v, n_aux=naux, order=order, eps=self._arrays[0].ctypes.data,
-                      B_oo=self._arrays[1].ctypes.data, B_ov=self._arrays[2].ctypes.data,
-                      B_vv=self._arrays[3].ctypes.data,
-                      dip=self._arrays[4].ctypes.data if dip is not None else None, device_ptrs=0)
+        if device_ptrs:
+            # torch device tensors (float64, contiguous), already resident in HBM
+            arrs = [eps, B_oo, B_ov, B_vv] + ([dip] if dip is not None else [])
+            for a in arrs:
+                if not (a.is_cuda and a.is_contiguous()) or str(a.dtype) != "torch.float64":
+                    raise ValueError("device inputs must be contiguous float64 device tensors")
+            ptr = [a.data_ptr() for a in arrs]
+            naux, o, v = B_ov.shape
+        else:
+            arrs = [_f64(eps), _f64(B_oo), _f64(B_ov), _f64(B_vv)] + ([_f64(dip)] if dip is not None else [])
+            ptr = [a.ctypes.data for a in arrs]
+            naux, o, v = arrs[2].shape
+        self._arrays = arrs
+        s = pp_system(n_occ=o, n_vir=v, n_aux=naux, order=order, eps=ptr[0], B_oo=ptr[1], B_ov=ptr[2],
+                      B_vv=ptr[3], dip=ptr[4] if dip is not None else None, device_ptrs=1 if device_ptrs else 0)
         opt = options if options is not None else default_options(**kw)
         h = C.c_void_p()
         st = L.pp_setup(C.byref(s), C.byref(opt), C.byref(h))
@@ -194,6 +213,16 @@ class Handle:
                  residual=np.array(info.residual[:n_roots]), converged=np.array(info.converged[:n_roots]),
                  status=st)
         return e, vec, f, d
+
+    def stats(self) -> dict:
+        st = pp_stats()
+        _check(lib().pp_get_stats(self.h, C.byref(st)), self.h)
+        return dict(product_flops=st.product_flops, product_seconds=st.product_seconds,
+                    product_vectors=st.product_vectors, hhat_flops=st.hhat_flops, hhat_seconds=st.hhat_seconds,
+                    hhat_launches=st.hhat_launches)
+
+    def reset_stats(self):
+        _check(lib().pp_reset_stats(self.h), self.h)
 
     def mp2_energy(self) -> float:
         return lib().pp_mp2_energy(self.h)

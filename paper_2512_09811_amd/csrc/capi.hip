@@ -197,6 +197,29 @@ pp_status pp_window_solve(pp_handle* h, double omega0, int32_t n_roots, double* 
   });
 }
 
+pp_status pp_get_stats(pp_handle* h, pp_stats* st) {
+  if (!h || !h->ctx || !st) return PP_EINVAL;
+  return guarded(&h->err, [&] {
+    PPW_HIP(hipSetDevice(h->ctx->device));
+    h->ctx->resolve_stats();
+    const ppw::SigmaStats& s = h->ctx->stats;
+    st->product_flops = s.flops;
+    st->product_seconds = s.seconds;
+    st->product_vectors = s.vectors;
+    st->hhat_flops = s.hhat_flops;
+    st->hhat_seconds = s.hhat_seconds;
+    st->hhat_launches = s.hhat_launches;
+  });
+}
+
+pp_status pp_reset_stats(pp_handle* h) {
+  if (!h || !h->ctx) return PP_EINVAL;
+  return guarded(&h->err, [&] {
+    h->ctx->resolve_stats();
+    h->ctx->stats = ppw::SigmaStats{};
+  });
+}
+
 double pp_mp2_energy(const pp_handle* h) { return (h && h->ctx) ? h->ctx->emp2 : 0.0; }
 
 uint64_t pp_device_bytes(const pp_handle* h) { return (h && h->ctx) ? h->ctx->arena.used() : 0; }

@@ -73,6 +73,12 @@ void gemm_f64(const GemmDesc& d, double alpha, const double* A, const double* B,
 void gemm_f32(const GemmDesc& d, float alpha, const float* A, const float* B, float beta, float* C,
               hipStream_t s, Workspace ws = {});
 
+// Same kernels under a separate symbol, used for the amplitude contraction H = tau G.
+void gemm_f64_hhat(const GemmDesc& d, double alpha, const double* A, const double* B, double beta, double* C,
+                   hipStream_t s, Workspace ws = {});
+void gemm_f32_hhat(const GemmDesc& d, float alpha, const float* A, const float* B, float beta, float* C,
+                   hipStream_t s, Workspace ws = {});
+
 // Algorithmic flop count of a GemmDesc (2 per multiply-add).
 inline double gemm_flops(const GemmDesc& d) {
   return 2.0 * d.M * (double)d.N * d.K * d.KB * d.nb1 * d.nb2;

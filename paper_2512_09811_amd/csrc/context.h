@@ -88,6 +88,61 @@ struct SigmaStats {
   long hhat_launches = 0;
 };
 
+// HIP events recorded around product passes and around the dominant GEMM, kept
+// unresolved (no host synchronization in the hot path) until stats are read.
+class EventLog {
+ public:
+  ~EventLog() {
+    for (auto& r : recs_) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    for (auto e : pool_) (void)hipEventDestroy(e);
+  }
+  int start(hipStream_t s) {
+    Rec r{get(), get(), 0, 0.0};
+    PPW_HIP(hipEventRecord(r.a, s));
+    recs_.push_back(r);
+    return (int)recs_.size() - 1;
+  }
+  void stop(int i, hipStream_t s, int kind) {
+    recs_[i].kind = kind;
+    PPW_HIP(hipEventRecord(recs_[i].b, s));
+  }
+  // synchronizes on the recorded events and adds elapsed seconds per kind
+  void resolve(double* seconds_by_kind, int nkinds) {
+    for (auto& r : recs_) {
+      PPW_HIP(hipEventSynchronize(r.b));
+      float ms = 0.f;
+      PPW_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+      if (r.kind >= 0 && r.kind < nkinds) seconds_by_kind[r.kind] += 1e-3 * ms;
+      pool_.push_back(r.a);
+      pool_.push_back(r.b);
+    }
+    recs_.clear();
+  }
+  size_t pending() const { return recs_.size(); }
+
+ private:
+  struct Rec {
+    hipEvent_t a, b;
+    int kind;
+    double flops;
+  };
+  hipEvent_t get() {
+    if (!pool_.empty()) {
+      hipEvent_t e = pool_.back();
+      pool_.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    PPW_HIP(hipEventCreate(&e));
+    return e;
+  }
+  std::vector<Rec> recs_;
+  std::vector<hipEvent_t> pool_;
+};
+
 struct Context {
   int o = 0, v = 0, naux = 0, order = 0;
   long N = 0;
@@ -131,7 +186,16 @@ struct Context {
   size_t ws_bytes = 0;
 
   SigmaStats stats;
+  EventLog events;
   std::string last_error;
+
+  // folds pending event timings into stats (synchronizes on them)
+  void resolve_stats() {
+    double sec[2] = {0.0, 0.0};
+    events.resolve(sec, 2);
+    stats.seconds += sec[0];
+    stats.hhat_seconds += sec[1];
+  }
 
   ~Context();
 };

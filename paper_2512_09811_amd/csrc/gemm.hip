@@ -67,7 +67,9 @@ __device__ __forceinline__ void tile_coords(int bid, int tiles_m, int tiles_n, i
   tn = r / gsize;
 }
 
-template <typename T, int BM, int BN, int BK>
+// TAG only distinguishes kernel symbols (the amplitude contraction gets its own,
+// so that profiles can attribute its time); the code is identical.
+template <typename T, int BM, int BN, int BK, int TAG>
 __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmDesc d, T alpha, const T* __restrict__ A,
                                                         const T* __restrict__ B, T beta, T* __restrict__ C,
                                                         T* __restrict__ W, int splitk) {
@@ -224,7 +226,7 @@ __global__ void splitk_reduce_kernel(GemmDesc d, T alpha, T beta, const T* __res
   }
 }
 
-template <typename T, int BM, int BN, int BK>
+template <typename T, int BM, int BN, int BK, int TAG = 0>
 void launch(const GemmDesc& d, T alpha, const T* A, const T* B, T beta, T* C, hipStream_t s, Workspace ws) {
   const int tiles_m = (d.M + BM - 1) / BM, tiles_n = (d.N + BN - 1) / BN;
   const long nbatch = (long)d.nb1 * d.nb2;
@@ -245,11 +247,11 @@ void launch(const GemmDesc& d, T alpha, const T* A, const T* B, T beta, T* C, hi
   }
   dim3 grid((unsigned)ntiles, (unsigned)nbatch, (unsigned)splitk);
   if (splitk == 1) {
-    gemm_kernel<T, BM, BN, BK><<<grid, kThreads, 0, s>>>(d, alpha, A, B, beta, C, nullptr, 1);
+    gemm_kernel<T, BM, BN, BK, TAG><<<grid, kThreads, 0, s>>>(d, alpha, A, B, beta, C, nullptr, 1);
     PPW_LAUNCH_CHECK();
   } else {
     T* W = static_cast<T*>(ws.ptr);
-    gemm_kernel<T, BM, BN, BK><<<grid, kThreads, 0, s>>>(d, alpha, A, B, beta, C, W, splitk);
+    gemm_kernel<T, BM, BN, BK, TAG><<<grid, kThreads, 0, s>>>(d, alpha, A, B, beta, C, W, splitk);
     PPW_LAUNCH_CHECK();
     const long n = (long)d.M * d.N * nbatch;
     const int blocks = (int)std::min<long>((n + 255) / 256, 8192);
@@ -258,16 +260,16 @@ void launch(const GemmDesc& d, T alpha, const T* A, const T* B, T beta, T* C, hi
   }
 }
 
-template <typename T>
+template <typename T, int TAG = 0>
 void gemm_dispatch(const GemmDesc& d, T alpha, const T* A, const T* B, T beta, T* C, hipStream_t s,
                    Workspace ws) {
   if (d.M <= 0 || d.N <= 0 || d.nb1 <= 0 || d.nb2 <= 0) return;
   if (d.K <= 0 || d.KB <= 0) throw InvalidArg("gemm: empty reduction");
   const bool big = d.M >= 96 && d.N >= 96;
   if (big)
-    launch<T, 128, 128, 16>(d, alpha, A, B, beta, C, s, ws);
+    launch<T, 128, 128, 16, TAG>(d, alpha, A, B, beta, C, s, ws);
   else
-    launch<T, 64, 64, 16>(d, alpha, A, B, beta, C, s, ws);
+    launch<T, 64, 64, 16, TAG>(d, alpha, A, B, beta, C, s, ws);
 }
 
 }  // namespace
@@ -275,6 +277,16 @@ void gemm_dispatch(const GemmDesc& d, T alpha, const T* A, const T* B, T beta, T
 void gemm_f64(const GemmDesc& d, double alpha, const double* A, const double* B, double beta, double* C,
               hipStream_t s, Workspace ws) {
   gemm_dispatch<double>(d, alpha, A, B, beta, C, s, ws);
+}
+
+void gemm_f64_hhat(const GemmDesc& d, double alpha, const double* A, const double* B, double beta, double* C,
+                   hipStream_t s, Workspace ws) {
+  gemm_dispatch<double, 1>(d, alpha, A, B, beta, C, s, ws);
+}
+
+void gemm_f32_hhat(const GemmDesc& d, float alpha, const float* A, const float* B, float beta, float* C,
+                   hipStream_t s, Workspace ws) {
+  gemm_dispatch<float, 1>(d, alpha, A, B, beta, C, s, ws);
 }
 
 void gemm_f32(const GemmDesc& d, float alpha, const float* A, const float* B, float beta, float* C,

@@ -257,26 +257,7 @@ void grow_workspace(Context& c, int k) {
   c.kcap = k;
 }
 
-struct EventTimer {
-  hipEvent_t a = nullptr, b = nullptr;
-  hipStream_t s;
-  explicit EventTimer(hipStream_t s_) : s(s_) {
-    PPW_HIP(hipEventCreate(&a));
-    PPW_HIP(hipEventCreate(&b));
-    PPW_HIP(hipEventRecord(a, s));
-  }
-  float stop() {
-    PPW_HIP(hipEventRecord(b, s));
-    PPW_HIP(hipEventSynchronize(b));
-    float ms = 0.f;
-    PPW_HIP(hipEventElapsedTime(&ms, a, b));
-    return ms;
-  }
-  ~EventTimer() {
-    if (a) (void)hipEventDestroy(a);
-    if (b) (void)hipEventDestroy(b);
-  }
-};
+
 
 }  // namespace
 
@@ -291,7 +272,8 @@ void sigma_core(Context& c, int order, int k, const double* V, double* AV, doubl
     return;
   }
   grow_workspace(c, k);
-  EventTimer timer(s);
+  if (c.events.pending() > 4096) c.resolve_stats();
+  const int ev_pass = c.events.start(s);
   double* cP = c.w_c;
   double* J = c.w_J;
   double* G = c.w_G;
@@ -395,12 +377,13 @@ void sigma_core(Context& c, int order, int k, const double* V, double* AV, doubl
         gemm_f64(d, -1.0, c.Boo_t + (size_t)i0 * X, H, 1.0, BV, s, c.ws);
       }
     };
-    EventTimer th(s);
     double hflops = 0.0;
     if (c.tau) {
       // H[(i,c)][(q,P)] = sum_(j,d) tau[(i,c)][(j,d)] G[(q,P)][(j,d)]
       GemmDesc d = gd((int)N, (int)kX, (int)N, 0, N, 1, N, kX);
-      gemm_f64(d, 1.0, c.tau, G, 0.0, c.w_H, s, c.ws);
+      const int ev = c.events.start(s);
+      gemm_f64_hhat(d, 1.0, c.tau, G, 0.0, c.w_H, s, c.ws);
+      c.events.stop(ev, s, 1);
       hflops += gemm_flops(d);
       c.stats.hhat_launches += 1;
       outputs(c.w_H, 0, o);
@@ -411,13 +394,14 @@ void sigma_core(Context& c, int order, int k, const double* V, double* AV, doubl
         gemm_f64(gd(nb * v, (int)N, X, 1, N, 0, N, N), 1.0, c.Bov + (size_t)i0 * v, c.Bov, 0.0, c.w_S, s, c.ws);
         tau_strip(c.w_S, o, v, i0, nb, c.eps_o, c.eps_v, c.w_tau, nullptr, nullptr, nullptr, nullptr, s);
         GemmDesc d = gd(nb * v, (int)kX, (int)N, 0, N, 1, N, kX);
-        gemm_f64(d, 1.0, c.w_tau, G, 0.0, c.w_H, s, c.ws);
+        const int ev = c.events.start(s);
+        gemm_f64_hhat(d, 1.0, c.w_tau, G, 0.0, c.w_H, s, c.ws);
+        c.events.stop(ev, s, 1);
         hflops += gemm_flops(d);
         c.stats.hhat_launches += 1;
         outputs(c.w_H, i0, nb);
       }
     }
-    c.stats.hhat_seconds += th.stop() * 1e-3;
     c.stats.hhat_flops += hflops;
     // delta-type terms: P1 = V Gv, P2 = V Ev, P3 = Go V, P4 = Eo V
     gemm_f64(gd(k * o, v, v, 0, v, 0, v, v), 1.0, V, c.Gv, 0.0, P1, s, c.ws);
@@ -432,7 +416,7 @@ void sigma_core(Context& c, int order, int k, const double* V, double* AV, doubl
     }
   }
   sigma_assemble(o, v, k, order, c.eps_o, c.eps_v, V, J, P1, P2, P3, P4, AV, BV, SV, s);
-  c.stats.seconds += timer.stop() * 1e-3;
+  c.events.stop(ev_pass, s, 0);
   c.stats.flops += sigma_flops(c, order, k);
   c.stats.vectors += k;
 }

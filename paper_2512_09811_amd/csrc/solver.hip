@@ -676,6 +676,7 @@ Solver::Ritz Solver::rayleigh_ritz() {
 
 void Solver::run(double* energies, double* vectors, double* osc, pp_solve_info* info) {
   const auto t0 = std::chrono::steady_clock::now();
+  c_.resolve_stats();
   const double sig0 = c_.stats.seconds, flop0 = c_.stats.flops;
   // start block: m top-half pairs with the smallest |A_ii - w0 S_ii|
   auto dA = fetch(c_.dA, N_);
@@ -813,6 +814,7 @@ void Solver::run(double* energies, double* vectors, double* osc, pp_solve_info* 
     for (int q = 0; q < r; ++q) osc[q] = f[q];
   }
   PPW_HIP(hipStreamSynchronize(s_));
+  c_.resolve_stats();
   if (info) {
     info->cycles = cycle;
     info->basis = nb_;

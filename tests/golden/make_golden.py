@@ -1,0 +1,49 @@
+"""Writes the stored expected values of the window-solve workloads.
+
+Calls only the FP64 oracle (dense assembly and exact pencil diagonalisation) on
+the seeded synthetic systems; no value comes from the HIP path.  Usage:
+    python tests/golden/make_golden.py [workload ...]
+Each workload produces tests/golden/<workload>.json with, per window, the
+oracle's roots nearest omega0 (Ha, ascending) and their dipole oscillator
+strengths.
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from synth.gen import CONFIGS, WINDOWS, gen_config  # noqa: E402
+from oracle import dense, pencil  # noqa: E402
+
+
+def make(name):
+    cfg = CONFIGS[name]
+    omegas, nr = WINDOWS[name]
+    t0 = time.time()
+    sys_ = gen_config(name)
+    A, B, S = dense.assemble(sys_, cfg["order"])
+    om, X, Y = pencil.solve_all(A, B, S)
+    out = dict(workload=name, order=cfg["order"], o=cfg["o"], v=cfg["v"], naux=cfg["naux"], seed=cfg["seed"],
+               mp2_energy=dense.mp2_energy(sys_) if cfg["order"] >= 2 else 0.0, windows=[])
+    for w0 in omegas:
+        idx = pencil.select_window(om, float(w0), nr)
+        idx = idx[np.argsort(om[idx])]
+        f = pencil.oscillator_strengths(om[idx], X[:, idx], Y[:, idx], sys_.dip)
+        out["windows"].append(dict(omega0=float(w0), n_roots=int(nr), energies=[float(x) for x in om[idx]],
+                                   osc=[float(x) for x in f]))
+    out["oracle_seconds"] = time.time() - t0
+    path = os.path.join(HERE, f"{name}.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print("wrote", path, f"({out['oracle_seconds']:.1f} s)")
+
+
+if __name__ == "__main__":
+    names = sys.argv[1:] or ["rpa1_o8_v24_x64", "mp2_o40_v160_x600"]
+    for n in names:
+        make(n)
