@@ -11,6 +11,7 @@
 // recurrence run by one thread and each rotation sequence applied to all rows of
 // the eigenvector matrix in parallel.  Eigenvalues are returned ascending.
 #include <cfloat>
+#include <vector>
 
 #include "solver.h"
 
@@ -286,6 +287,279 @@ __global__ __launch_bounds__(kT) void trinv_kernel(int n, const double* __restri
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Spectrum slicing for the projected problem (only the eigenpairs near a target)
+// ---------------------------------------------------------------------------
+
+// Householder tridiagonalization (one workgroup).  d[n], e[n] (e[i] couples i, i+1);
+// Hh[k][n] holds the unit reflector u_k of step k (zero in entries <= k).
+__global__ __launch_bounds__(kT) void tridiag_kernel(int n, const double* __restrict__ A, double* __restrict__ W,
+                                                     double* __restrict__ dout, double* __restrict__ eout,
+                                                     double* __restrict__ Hh) {
+  __shared__ double u[kMaxN];
+  __shared__ double q[kMaxN];
+  __shared__ double red[40];
+  const int tid = threadIdx.x;
+  const long nn = (long)n * n;
+  for (long i = tid; i < nn; i += kT) {
+    W[i] = A[i];
+    Hh[i] = 0.0;
+  }
+  __syncthreads();
+  for (int k = 0; k + 2 < n; ++k) {
+    const int m = n - k - 1;
+    double part = 0.0;
+    for (int r = tid; r < m; r += kT) {
+      const double x = W[(long)(k + 1 + r) * n + k];
+      part += x * x;
+    }
+    const double xx = block_reduce_sum(part, red);
+    const double x0 = W[(long)(k + 1) * n + k];
+    const double xnorm = sqrt(xx);
+    if (tid == 0) dout[k] = W[(long)k * n + k];
+    if (xnorm == 0.0) {
+      if (tid == 0) eout[k] = 0.0;
+      __syncthreads();
+      continue;
+    }
+    const double alpha = x0 > 0 ? -xnorm : xnorm;
+    const double vnorm = sqrt(2.0 * xx - 2.0 * x0 * alpha);
+    for (int r = tid; r < m; r += kT) {
+      const double x = W[(long)(k + 1 + r) * n + k];
+      u[r] = (r == 0 ? x - alpha : x) / vnorm;
+    }
+    __syncthreads();
+    for (int r = tid; r < m; r += kT) {
+      double acc = 0.0;
+      for (int cc = 0; cc < m; ++cc) acc += W[(long)(k + 1 + cc) * n + (k + 1 + r)] * u[cc];
+      q[r] = acc;
+    }
+    __syncthreads();
+    double kp = 0.0;
+    for (int r = tid; r < m; r += kT) kp += u[r] * q[r];
+    const double K = block_reduce_sum(kp, red);
+    for (int r = tid; r < m; r += kT) q[r] = q[r] - K * u[r];
+    __syncthreads();
+    const long mm = (long)m * m;
+    for (long idx = tid; idx < mm; idx += kT) {
+      const int r = (int)(idx / m), cc = (int)(idx % m);
+      W[(long)(k + 1 + r) * n + (k + 1 + cc)] -= 2.0 * (u[r] * q[cc] + q[r] * u[cc]);
+    }
+    for (int r = tid; r < m; r += kT) Hh[(long)k * n + k + 1 + r] = u[r];
+    if (tid == 0) eout[k] = alpha;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (n >= 2) {
+      dout[n - 2] = W[(long)(n - 2) * n + (n - 2)];
+      eout[n - 2] = W[(long)(n - 1) * n + (n - 2)];
+    }
+    dout[n - 1] = W[(long)(n - 1) * n + (n - 1)];
+    eout[n - 1] = 0.0;
+  }
+}
+
+// number of eigenvalues of the tridiagonal (d, e) below x (Sturm sequence)
+__device__ int sturm_count(int n, const double* d, const double* e, double x, double pivmin) {
+  int c = 0;
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  if (q < 0) ++c;
+  for (int i = 1; i < n; ++i) {
+    q = d[i] - x - e[i - 1] * e[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    if (q < 0) ++c;
+  }
+  return c;
+}
+
+// Eigenvalues lo..lo+p-1 of the tridiagonal around 'target' by bisection (one per
+// thread) and their vectors by inverse iteration with partially pivoted LU.
+// V[t][n]: vector t; lam[t]; work: 6 n doubles per thread.
+__global__ __launch_bounds__(kT) void slice_kernel(int n, const double* __restrict__ d, const double* __restrict__ e,
+                                                   double target, int p, double* __restrict__ lam,
+                                                   double* __restrict__ V, double* __restrict__ work) {
+  __shared__ double sd[kMaxN], se[kMaxN];
+  __shared__ double bounds[3];
+  __shared__ int lo_s;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < n; i += kT) {
+    sd[i] = d[i];
+    se[i] = e[i];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double gl = sd[0], gu = sd[0], emax = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const double r = (i > 0 ? fabs(se[i - 1]) : 0.0) + (i + 1 < n ? fabs(se[i]) : 0.0);
+      gl = fmin(gl, sd[i] - r);
+      gu = fmax(gu, sd[i] + r);
+      if (i + 1 < n) emax = fmax(emax, se[i] * se[i]);
+    }
+    const double span = fmax(gu - gl, 1e-300);
+    bounds[0] = gl - 1e-14 * span;
+    bounds[1] = gu + 1e-14 * span;
+    bounds[2] = fmax(DBL_MIN, 1e-300 + 4.0 * DBL_MIN * fmax(1.0, emax));
+    const int j0 = sturm_count(n, sd, se, target, bounds[2]);
+    int lo = j0 - p / 2;
+    lo = max(0, min(lo, n - p));
+    lo_s = lo;
+  }
+  __syncthreads();
+  const double pivmin = bounds[2];
+  const double scale = fmax(fabs(bounds[0]), fabs(bounds[1]));
+  if (tid < p) {
+    const int idx = lo_s + tid;  // want the idx-th smallest (0-based)
+    double a = bounds[0], b = bounds[1];
+    for (int it = 0; it < 200 && (b - a) > 4.0 * DBL_EPSILON * fmax(fabs(a), fabs(b)) + DBL_MIN; ++it) {
+      const double mid = 0.5 * (a + b);
+      if (sturm_count(n, sd, se, mid, pivmin) > idx)
+        b = mid;
+      else
+        a = mid;
+    }
+    const double lmb = 0.5 * (a + b);
+    lam[tid] = lmb;
+    // inverse iteration on (T - lmb I)
+    double* dl = work + (long)tid * 6 * n;
+    double* dd = dl + n;
+    double* du = dd + n;
+    double* du2 = du + n;
+    double* x = du2 + n;
+    int* piv = (int*)(x + n);  // n ints fit in n doubles
+    const double pert = 1e-15 * fmax(scale, 1e-300);
+    for (int i = 0; i < n; ++i) {
+      dd[i] = sd[i] - lmb;
+      if (i + 1 < n) {
+        dl[i] = se[i];
+        du[i] = se[i];
+      }
+      du2[i] = 0.0;
+      piv[i] = i;
+    }
+    for (int i = 0; i + 1 < n; ++i) {
+      if (fabs(dd[i]) >= fabs(dl[i])) {
+        if (dd[i] == 0.0) dd[i] = pert;
+        const double f = dl[i] / dd[i];
+        dl[i] = f;
+        dd[i + 1] -= f * du[i];
+      } else {
+        const double f = dd[i] / dl[i];
+        dd[i] = dl[i];
+        dl[i] = f;
+        const double tmp = du[i];
+        du[i] = dd[i + 1];
+        dd[i + 1] = tmp - f * dd[i + 1];
+        if (i + 2 < n) {
+          du2[i] = du[i + 1];
+          du[i + 1] = -f * du[i + 1];
+        }
+        piv[i] = i + 1;
+      }
+    }
+    if (dd[n - 1] == 0.0) dd[n - 1] = pert;
+    // deterministic start vector
+    for (int i = 0; i < n; ++i) x[i] = 1.0 + 0.5 * sin(0.7 * i + 1.3 * tid + 0.1);
+    for (int iter = 0; iter < 4; ++iter) {
+      for (int i = 0; i + 1 < n; ++i) {
+        if (piv[i] == i) {
+          x[i + 1] -= dl[i] * x[i];
+        } else {
+          const double t = x[i];
+          x[i] = x[i + 1];
+          x[i + 1] = t - dl[i] * x[i];
+        }
+      }
+      x[n - 1] /= dd[n - 1];
+      if (n >= 2) x[n - 2] = (x[n - 2] - du[n - 2] * x[n - 1]) / dd[n - 2];
+      for (int i = n - 3; i >= 0; --i) x[i] = (x[i] - du[i] * x[i + 1] - du2[i] * x[i + 2]) / dd[i];
+      double s2 = 0.0;
+      for (int i = 0; i < n; ++i) s2 += x[i] * x[i];
+      const double inv = 1.0 / sqrt(s2);
+      for (int i = 0; i < n; ++i) x[i] *= inv;
+    }
+    for (int i = 0; i < n; ++i) V[(long)tid * n + i] = x[i];
+  }
+}
+
+// T1[t][j] = UG[t][first + j] / sqrt(w[first + j])  (p x q, ld q)
+__global__ void scale_keep_kernel(int p, int first, const double* __restrict__ U, const double* __restrict__ w,
+                                  double* __restrict__ T1) {
+  const int q = p - first;
+  for (int idx = threadIdx.x; idx < p * q; idx += blockDim.x) {
+    const int t = idx / q, j = idx % q;
+    T1[idx] = U[(long)t * p + first + j] / sqrt(w[first + j]);
+  }
+}
+
+__global__ void symmetrize_small_kernel(int n, double* A) {
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    const int r = idx / n, c = idx % n;
+    if (c > r) {
+      const double m = 0.5 * (A[r * n + c] + A[c * n + r]);
+      A[r * n + c] = m;
+      A[c * n + r] = m;
+    }
+  }
+}
+
+// Y[t][i] = (T V)[t][i] for the tridiagonal (d, e) and p row vectors of length n
+__global__ void tridiag_apply_kernel(int n, int p, const double* __restrict__ d, const double* __restrict__ e,
+                                     const double* __restrict__ V, double* __restrict__ Y) {
+  const long tot = (long)n * p;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < tot; idx += (long)gridDim.x * blockDim.x) {
+    const int t = (int)(idx / n), i = (int)(idx % n);
+    const double* v = V + (long)t * n;
+    double y = d[i] * v[i];
+    if (i > 0) y += e[i - 1] * v[i - 1];
+    if (i + 1 < n) y += e[i] * v[i + 1];
+    Y[idx] = y;
+  }
+}
+
+// Z[r][j] = (H_0 ... H_{n-3} v_j)[r]: one workgroup per vector
+__global__ __launch_bounds__(256) void backtransform_kernel(int n, int p, const double* __restrict__ Hh,
+                                                            const double* __restrict__ V, double* __restrict__ Z) {
+  __shared__ double v[kMaxN];
+  __shared__ double red[40];
+  const int j = blockIdx.x;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < n; i += blockDim.x) v[i] = V[(long)j * n + i];
+  __syncthreads();
+  for (int k = n - 3; k >= 0; --k) {
+    const double* u = Hh + (long)k * n;
+    double part = 0.0;
+    for (int i = k + 1 + tid; i < n; i += blockDim.x) part += u[i] * v[i];
+    // block reduction over 256 threads
+    for (int off = 32; off > 0; off >>= 1) part += __shfl_down(part, off, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = part;
+    __syncthreads();
+    const double dot = red[0] + red[1] + red[2] + red[3];
+    for (int i = k + 1 + tid; i < n; i += blockDim.x) v[i] -= 2.0 * dot * u[i];
+    __syncthreads();
+  }
+  for (int i = tid; i < n; i += blockDim.x) Z[(long)i * p + j] = v[i];
+}
+
+// L^T X = B, one workgroup per right-hand side (column j of B[n][p])
+__global__ __launch_bounds__(256) void trsm_lt_kernel(int n, const double* __restrict__ L, int p, double* __restrict__ B) {
+  __shared__ double b[kMaxN];
+  const int j = blockIdx.x;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < n; i += blockDim.x) b[i] = B[(long)i * p + j];
+  __syncthreads();
+  for (int i = n - 1; i >= 0; --i) {
+    const double xi = b[i] / L[(long)i * n + i];
+    __syncthreads();
+    if (tid == 0) b[i] = xi;
+    // b[k] -= L[i][k] x_i for k < i   (row i of L, contiguous)
+    for (int k = tid; k < i; k += blockDim.x) b[k] -= L[(long)i * n + k] * xi;
+    __syncthreads();
+  }
+  for (int i = tid; i < n; i += blockDim.x) B[(long)i * p + j] = b[i];
+}
+
 }  // namespace
 
 void small_syev(int n, const double* A, double* w, double* Z, hipStream_t s, double* scratch) {
@@ -299,6 +573,73 @@ void small_syev(int n, const double* A, double* w, double* Z, hipStream_t s, dou
     (void)hipFree(ws);
   }
   if (e != hipSuccess) throw DeviceError(std::string("syev launch: ") + hipGetErrorString(e));
+}
+
+size_t partial_syev_scratch(int n, int p) {
+  return (size_t)2 * n * n + 2 * (size_t)n + 4 * (size_t)p * n + 6 * (size_t)n * p + 8 * (size_t)p * p + 64;
+}
+
+int partial_syev(int n, const double* A, double target, int p, double* lam, double* Z, double* scratch,
+                 hipStream_t s) {
+  if (n < 1 || n > kMaxN || p < 1 || p > 64 || p > n) throw InvalidArg("partial_syev: size out of range");
+  double* W = scratch;
+  double* Hh = W + (size_t)n * n;
+  double* d = Hh + (size_t)n * n;
+  double* e = d + n;
+  double* V = e + n;
+  double* V1 = V + (size_t)p * n;
+  double* Y = V1 + (size_t)p * n;
+  double* V2 = Y + (size_t)p * n;
+  double* work = V2 + (size_t)p * n;
+  double* G = work + (size_t)6 * n * p;
+  double* UG = G + (size_t)p * p;
+  double* T1 = UG + (size_t)p * p;
+  double* H = T1 + (size_t)p * p;
+  double* UH = H + (size_t)p * p;
+  double* wG = UH + (size_t)p * p;
+  double* eig_scr = wG + p;  // 2 p^2
+  tridiag_kernel<<<1, kT, 0, s>>>(n, A, W, d, e, Hh);
+  PPW_LAUNCH_CHECK();
+  slice_kernel<<<1, kT, 0, s>>>(n, d, e, target, p, lam, V, work);
+  PPW_LAUNCH_CHECK();
+  // Rayleigh-Ritz inside span(V): G = V V^T, symmetric orthonormalization, H = V1 T V1^T
+  GemmDesc g;
+  g.M = p; g.N = p; g.K = n; g.transA = 0; g.lda = n; g.transB = 1; g.ldb = n; g.ldc = p;
+  gemm_f64(g, 1.0, V, V, 0.0, G, s);
+  small_syev(p, G, wG, UG, s, eig_scr);
+  std::vector<double> wg(p);
+  PPW_HIP(hipMemcpyAsync(wg.data(), wG, sizeof(double) * p, hipMemcpyDeviceToHost, s));
+  PPW_HIP(hipStreamSynchronize(s));
+  int first = 0;
+  while (first < p && !(wg[first] > 1e-12 * wg[p - 1])) ++first;
+  const int q = p - first;
+  if (q == 0) throw Unstable("partial_syev: inverse iteration produced no independent vectors");
+  scale_keep_kernel<<<1, 256, 0, s>>>(p, first, UG, wG, T1);
+  PPW_LAUNCH_CHECK();
+  // V1[j][r] = sum_t T1[t][j] V[t][r]   (T1 is p x q, ld q)
+  GemmDesc a;
+  a.M = q; a.N = n; a.K = p; a.transA = 1; a.lda = q; a.transB = 0; a.ldb = n; a.ldc = n;
+  gemm_f64(a, 1.0, T1, V, 0.0, V1, s);
+  tridiag_apply_kernel<<<(n * q + 255) / 256, 256, 0, s>>>(n, q, d, e, V1, Y);
+  PPW_LAUNCH_CHECK();
+  GemmDesc h;
+  h.M = q; h.N = q; h.K = n; h.transA = 0; h.lda = n; h.transB = 1; h.ldb = n; h.ldc = q;
+  gemm_f64(h, 1.0, V1, Y, 0.0, H, s);
+  symmetrize_small_kernel<<<1, 256, 0, s>>>(q, H);
+  small_syev(q, H, lam, UH, s, eig_scr);
+  // V2[j][r] = sum_t UH[t][j] V1[t][r]
+  GemmDesc b;
+  b.M = q; b.N = n; b.K = q; b.transA = 1; b.lda = q; b.transB = 0; b.ldb = n; b.ldc = n;
+  gemm_f64(b, 1.0, UH, V1, 0.0, V2, s);
+  backtransform_kernel<<<q, 256, 0, s>>>(n, p, Hh, V2, Z);
+  PPW_LAUNCH_CHECK();
+  return q;
+}
+
+void small_trsm_lt(int n, const double* L, int p, double* B, hipStream_t s) {
+  if (n < 1 || n > kMaxN) throw InvalidArg("small_trsm_lt: n out of range");
+  trsm_lt_kernel<<<p, 256, 0, s>>>(n, L, p, B);
+  PPW_LAUNCH_CHECK();
 }
 
 void small_cholesky(int n, const double* A, double* L, int* info, hipStream_t s) {

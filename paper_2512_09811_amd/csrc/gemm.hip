@@ -67,20 +67,33 @@ __device__ __forceinline__ void tile_coords(int bid, int tiles_m, int tiles_n, i
   tn = r / gsize;
 }
 
+// LDS layouts (chosen per operand at compile time, FP64 64 banks x 4 B):
+//  * operand contiguous along k in global memory (A: transA = 0, B: transB = 1):
+//    tile stored [m][BK + 2]; a 16-lane group reads 16 rows at one k: bank offsets
+//    36 i (+2 for the next k group) are distinct, and the global->LDS writes are
+//    consecutive addresses.
+//  * operand contiguous along m (or n): tile stored [k][BM + 16]; rows of 16 lanes
+//    sit 32 banks apart, writes are consecutive.
 // TAG only distinguishes kernel symbols (the amplitude contraction gets its own,
 // so that profiles can attribute its time); the code is identical.
-template <typename T, int BM, int BN, int BK, int TAG>
-__global__ __launch_bounds__(kThreads) void gemm_kernel(GemmDesc d, T alpha, const T* __restrict__ A,
+template <typename T, int BM, int BN, int BK, bool AK, bool BKC, int TAG>
+__global__ __launch_bounds__(kThreads, 2) void gemm_kernel(GemmDesc d, T alpha, const T* __restrict__ A,
                                                         const T* __restrict__ B, T beta, T* __restrict__ C,
                                                         T* __restrict__ W, int splitk) {
   using acc_t = typename Mfma<T>::acc_t;
-  constexpr int PAD = 16 / sizeof(T);
+  constexpr int PK = 2;   // pad of k-contiguous tiles
+  constexpr int PM = 16;  // pad of m/n-contiguous tiles
   constexpr int WTM = BM / 2, WTN = BN / 2;
   constexpr int TM = WTM / 16, TN = WTN / 16;
   constexpr int LA = BM * BK / kThreads, LB = BN * BK / kThreads;
   static_assert(LA * kThreads == BM * BK && LB * kThreads == BN * BK, "tile/thread mismatch");
-  __shared__ T As[2][BK][BM + PAD];
-  __shared__ T Bs[2][BK][BN + PAD];
+  constexpr int SA = AK ? BM * (BK + PK) : BK * (BM + PM);
+  constexpr int SB = BKC ? BN * (BK + PK) : BK * (BN + PM);
+  __shared__ T As[2][SA];
+  __shared__ T Bs[2][SB];
+  // element (m, k) of an LDS tile
+  auto aidx = [](int m, int k) { return AK ? m * (BK + PK) + k : k * (BM + PM) + m; };
+  auto bidx = [](int n, int k) { return BKC ? n * (BK + PK) + k : k * (BN + PM) + n; };
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -111,31 +124,34 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmDesc d, T alpha, con
     for (int j = 0; j < TN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
   T ra[LA], rb[LB];
-  const bool tA = d.transA != 0, tB = d.transB != 0;
-
+  // Tile base pointers are advanced per iteration (wave-uniform 64-bit); per-element
+  // offsets inside a tile are 32-bit (row * ld + k stays below 2^31 for every shape
+  // the library issues), which keeps register pressure low enough for 2 waves/SIMD.
+  const T* Atile = Ab + (AK ? (long)m0 * d.lda : (long)m0);
+  const T* Btile = Bb + (BKC ? (long)n0 * d.ldb : (long)n0);
+  const int lda32 = (int)d.lda, ldb32 = (int)d.ldb;
   auto load = [&](long it) {
     const int kb = (int)(it / nkt);
     const int k0 = (int)(it % nkt) * BK;
-    const T* Ak = Ab + kb * d.sAk;
-    const T* Bk = Bb + kb * d.sBk;
+    const T* Ak = Atile + kb * d.sAk + (AK ? (long)k0 : (long)k0 * d.lda);
+    const T* Bk = Btile + kb * d.sBk + (BKC ? (long)k0 : (long)k0 * d.ldb);
+    const int mrem = d.M - m0, nrem = d.N - n0, krem = d.K - k0;
 #pragma unroll
     for (int i = 0; i < LA; ++i) {
       const int e = i * kThreads + tid;
-      const int m = tA ? (e % BM) : (e / BK);
-      const int k = tA ? (e / BM) : (e % BK);
-      const int gm = m0 + m, gk = k0 + k;
+      const int m = AK ? (e / BK) : (e % BM);
+      const int k = AK ? (e % BK) : (e / BM);
       T v = T(0);
-      if (gm < d.M && gk < d.K) v = tA ? Ak[(long)gk * d.lda + gm] : Ak[(long)gm * d.lda + gk];
+      if (m < mrem && k < krem) v = Ak[AK ? (m * lda32 + k) : (k * lda32 + m)];
       ra[i] = v;
     }
 #pragma unroll
     for (int i = 0; i < LB; ++i) {
       const int e = i * kThreads + tid;
-      const int n = tB ? (e / BK) : (e % BN);
-      const int k = tB ? (e % BK) : (e / BN);
-      const int gn = n0 + n, gk = k0 + k;
+      const int n = BKC ? (e / BK) : (e % BN);
+      const int k = BKC ? (e % BK) : (e / BN);
       T v = T(0);
-      if (gn < d.N && gk < d.K) v = tB ? Bk[(long)gn * d.ldb + gk] : Bk[(long)gk * d.ldb + gn];
+      if (n < nrem && k < krem) v = Bk[BKC ? (n * ldb32 + k) : (k * ldb32 + n)];
       rb[i] = v;
     }
   };
@@ -143,16 +159,16 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmDesc d, T alpha, con
 #pragma unroll
     for (int i = 0; i < LA; ++i) {
       const int e = i * kThreads + tid;
-      const int m = tA ? (e % BM) : (e / BK);
-      const int k = tA ? (e / BM) : (e % BK);
-      As[buf][k][m] = ra[i];
+      const int m = AK ? (e / BK) : (e % BM);
+      const int k = AK ? (e % BK) : (e / BM);
+      As[buf][aidx(m, k)] = ra[i];
     }
 #pragma unroll
     for (int i = 0; i < LB; ++i) {
       const int e = i * kThreads + tid;
-      const int n = tB ? (e / BK) : (e % BN);
-      const int k = tB ? (e % BK) : (e / BN);
-      Bs[buf][k][n] = rb[i];
+      const int n = BKC ? (e / BK) : (e % BN);
+      const int k = BKC ? (e % BK) : (e / BN);
+      Bs[buf][bidx(n, k)] = rb[i];
     }
   };
 
@@ -169,9 +185,9 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmDesc d, T alpha, con
         const int kr = kk + (lane >> 4);
         T a[TM], b[TN];
 #pragma unroll
-        for (int i = 0; i < TM; ++i) a[i] = As[buf][kr][wm * WTM + i * 16 + (lane & 15)];
+        for (int i = 0; i < TM; ++i) a[i] = As[buf][aidx(wm * WTM + i * 16 + (lane & 15), kr)];
 #pragma unroll
-        for (int j = 0; j < TN; ++j) b[j] = Bs[buf][kr][wn * WTN + j * 16 + (lane & 15)];
+        for (int j = 0; j < TN; ++j) b[j] = Bs[buf][bidx(wn * WTN + j * 16 + (lane & 15), kr)];
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -226,11 +242,14 @@ __global__ void splitk_reduce_kernel(GemmDesc d, T alpha, T beta, const T* __res
   }
 }
 
-template <typename T, int BM, int BN, int BK, int TAG = 0>
+template <typename T, int BM, int BN, int BK, bool AK, bool BKC, int TAG>
 void launch(const GemmDesc& d, T alpha, const T* A, const T* B, T beta, T* C, hipStream_t s, Workspace ws) {
   const int tiles_m = (d.M + BM - 1) / BM, tiles_n = (d.N + BN - 1) / BN;
   const long nbatch = (long)d.nb1 * d.nb2;
   if (nbatch > 65535) throw InvalidArg("gemm: batch count exceeds 65535");
+  // per-tile element offsets are 32-bit inside the kernel
+  if ((double)d.lda * std::max(BM, BK) + d.K >= 2147483647.0 || (double)d.ldb * std::max(BN, BK) + d.K >= 2147483647.0)
+    throw InvalidArg("gemm: leading dimension too large for 32-bit tile offsets");
   const long ntiles = (long)tiles_m * tiles_n;
   const int nkt = (d.K + BK - 1) / BK;
   const long total = (long)d.KB * nkt;
@@ -247,11 +266,11 @@ void launch(const GemmDesc& d, T alpha, const T* A, const T* B, T beta, T* C, hi
   }
   dim3 grid((unsigned)ntiles, (unsigned)nbatch, (unsigned)splitk);
   if (splitk == 1) {
-    gemm_kernel<T, BM, BN, BK, TAG><<<grid, kThreads, 0, s>>>(d, alpha, A, B, beta, C, nullptr, 1);
+    gemm_kernel<T, BM, BN, BK, AK, BKC, TAG><<<grid, kThreads, 0, s>>>(d, alpha, A, B, beta, C, nullptr, 1);
     PPW_LAUNCH_CHECK();
   } else {
     T* W = static_cast<T*>(ws.ptr);
-    gemm_kernel<T, BM, BN, BK, TAG><<<grid, kThreads, 0, s>>>(d, alpha, A, B, beta, C, W, splitk);
+    gemm_kernel<T, BM, BN, BK, AK, BKC, TAG><<<grid, kThreads, 0, s>>>(d, alpha, A, B, beta, C, W, splitk);
     PPW_LAUNCH_CHECK();
     const long n = (long)d.M * d.N * nbatch;
     const int blocks = (int)std::min<long>((n + 255) / 256, 8192);
@@ -266,10 +285,24 @@ void gemm_dispatch(const GemmDesc& d, T alpha, const T* A, const T* B, T beta, T
   if (d.M <= 0 || d.N <= 0 || d.nb1 <= 0 || d.nb2 <= 0) return;
   if (d.K <= 0 || d.KB <= 0) throw InvalidArg("gemm: empty reduction");
   const bool big = d.M >= 96 && d.N >= 96;
-  if (big)
-    launch<T, 128, 128, 16, TAG>(d, alpha, A, B, beta, C, s, ws);
-  else
-    launch<T, 64, 64, 16, TAG>(d, alpha, A, B, beta, C, s, ws);
+  const bool ak = d.transA == 0, bk = d.transB != 0;
+#define PPW_GEMM_CASE(BMv, BNv, AKv, BKv)                                           \
+  if (ak == AKv && bk == BKv) {                                                     \
+    launch<T, BMv, BNv, 16, AKv, BKv, TAG>(d, alpha, A, B, beta, C, s, ws);         \
+    return;                                                                         \
+  }
+  if (big) {
+    PPW_GEMM_CASE(128, 128, true, true)
+    PPW_GEMM_CASE(128, 128, true, false)
+    PPW_GEMM_CASE(128, 128, false, true)
+    PPW_GEMM_CASE(128, 128, false, false)
+  } else {
+    PPW_GEMM_CASE(64, 64, true, true)
+    PPW_GEMM_CASE(64, 64, true, false)
+    PPW_GEMM_CASE(64, 64, false, true)
+    PPW_GEMM_CASE(64, 64, false, false)
+  }
+#undef PPW_GEMM_CASE
 }
 
 }  // namespace

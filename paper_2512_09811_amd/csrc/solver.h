@@ -33,3 +33,16 @@ void small_cholesky(int n, const double* A, double* L, int* info, hipStream_t s)
 void small_trinv(int n, const double* L, double* X, hipStream_t s);
 
 }  // namespace ppw
+
+namespace ppw {
+// Partial symmetric eigensolver for the projected problem: the p eigenpairs of the
+// n x n symmetric A (row-major, device) whose eigenvalues are nearest 'target'
+// (p <= n, p <= 64).  lam[p] ascending; Z[n][p] row-major (column j = vector j).
+// Work: 2 n^2 + 8 n p + 4 p^2 + 64 doubles of scratch (device).
+// Returns q <= p, the number of independent pairs found (columns 0..q-1 valid).
+int partial_syev(int n, const double* A, double target, int p, double* lam, double* Z, double* scratch,
+                 hipStream_t s);
+size_t partial_syev_scratch(int n, int p);
+// Solve L^T X = B for lower-triangular L (n x n) and p right-hand sides B[n][p] (row-major, in place).
+void small_trsm_lt(int n, const double* L, int p, double* B, hipStream_t s);
+}  // namespace ppw

@@ -300,6 +300,43 @@ __global__ void coeff_dots_kernel(int rows, int k, long ld, const double* __rest
   out[q] = s;
 }
 
+__global__ void identity_kernel(double* X, int n) {
+  GS_LOOP(idx, (long)n * n) X[idx] = (idx / n == idx % n) ? 1.0 : 0.0;
+}
+
+// out[0] = max |I - T| for an n x n matrix T
+__global__ void ns_residual_kernel(int n, const double* __restrict__ T, double* __restrict__ out) {
+  __shared__ double red[256];
+  double m = 0.0;
+  for (long idx = threadIdx.x; idx < (long)n * n; idx += blockDim.x)
+    m = fmax(m, fabs(T[idx] - ((idx / n == idx % n) ? 1.0 : 0.0)));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+__global__ void copy_cols_kernel(int rows, int cols, const double* __restrict__ src, long lds, double* __restrict__ dst,
+                                 long ldd) {
+  GS_LOOP(idx, (long)rows * cols) {
+    const int r = (int)(idx / cols), c = (int)(idx % cols);
+    dst[(long)r * ldd + c] = src[(long)r * lds + c];
+  }
+}
+
+// out[j] = sum_p (U[p][j]^2 + W[p][j]^2)
+__global__ void coeff_norms_kernel(int rows, int cols, const double* __restrict__ U, const double* __restrict__ W,
+                                   double* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= cols) return;
+  double s = 0.0;
+  for (int p = 0; p < rows; ++p) s += U[(long)p * cols + j] * U[(long)p * cols + j] + W[(long)p * cols + j] * W[(long)p * cols + j];
+  out[j] = s;
+}
+
 GemmDesc gd(int M, int N, int K, int tA, long lda, int tB, long ldb, long ldc) {
   GemmDesc d;
   d.M = M;
@@ -339,6 +376,7 @@ class Solver {
   hipStream_t s_;
   long N_;
   int nb_ = 0;
+  int rld_ = 1;  // columns (leading dimension) of the current Ritz coefficient matrices us_/ws_
   std::vector<void*> owned_;
   // basis and products [nbmax][N]
   double *Q_, *P0_, *P1_, *PS_, *Qs_, *P0s_, *P1s_, *PSs_;
@@ -423,8 +461,8 @@ class Solver {
     us_ = get<double>(bb, "us");
     ws_ = get<double>(bb, "ws");
     th_ = get<double>(nbmax_, "theta");
-    stats_ = get<double>((size_t)2 * nbmax_, "ritz stats");
-    eigscr_ = get<double>((size_t)2 * std::max(bb, kk), "eig scratch");
+    stats_ = get<double>(std::max((size_t)2 * nbmax_, (size_t)3 * 64), "ritz stats");
+    eigscr_ = get<double>(std::max((size_t)2 * std::max(bb, kk), partial_syev_scratch(nbmax_, 64)), "eig scratch");
     keep_ = get<int>(std::max(kmax_, nbmax_), "keep");
     ival_ = get<int>(4, "info");
     sel_ = get<int>(std::max(kmax_, nbmax_), "sel");
@@ -585,8 +623,8 @@ class Solver {
     const int kk = 2 * b;
     std::vector<int> cols(blk);
     upload(sel_, cols);
-    gather_cols_kernel<<<gridn((long)n * b), kB, 0, s_>>>(n, b, sel_, us_, n, tmp_, kk, 0);
-    gather_cols_kernel<<<gridn((long)n * b), kB, 0, s_>>>(n, b, sel_, ws_, n, tmp_, kk, b);
+    gather_cols_kernel<<<gridn((long)n * b), kB, 0, s_>>>(n, b, sel_, us_, rld_, tmp_, kk, 0);
+    gather_cols_kernel<<<gridn((long)n * b), kB, 0, s_>>>(n, b, sel_, ws_, rld_, tmp_, kk, b);
     // Gram of the coefficient vectors (n rows) and symmetric orthonormalization
     small_mm(kk, kk, n, tmp_, kk, 1, tmp_, kk, 0, g_, kk);
     symmetrize_kernel<<<gridn((long)kk * kk), kB, 0, s_>>>(g_, kk);
@@ -626,50 +664,70 @@ Solver::Ritz Solver::rayleigh_ritz() {
   symmetrize_kernel<<<gridn((long)n * n), kB, 0, s_>>>(Am_, n);
   symmetrize_kernel<<<gridn((long)n * n), kB, 0, s_>>>(Sp_, n);
   small_cholesky(n, Am_, L_, ival_, s_);
-  small_cholesky(n, Sp_, Ls_, ival_ + 1, s_);
-  auto info = fetch(ival_, 2);
+  // Sp^-1: the metric is the identity plus the (small) MP2 density correction, so
+  // Newton-Schulz X <- 2X - X Sp X from X = I converges quadratically; the Cholesky
+  // route is the fallback when |I - Sp X| does not reach rounding level.
+  identity_kernel<<<gridn((long)n * n), kB, 0, s_>>>(Spi_, n);
+  if (c_.order >= 2) {
+    for (int it = 0; it < 6; ++it) {
+      small_mm(n, n, n, Sp_, n, 0, Spi_, n, 0, tmp_, n);        // T = Sp X
+      small_mm(n, n, n, Spi_, n, 0, tmp_, n, 0, tmp2_, n);      // X T
+      axpby((long)n * n, 2.0, Spi_, 0.0, K_, s_);               // 2X
+      axpby((long)n * n, -1.0, tmp2_, 1.0, K_, s_);             // 2X - X T
+      PPW_HIP(hipMemcpyAsync(Spi_, K_, sizeof(double) * n * n, hipMemcpyDeviceToDevice, s_));
+    }
+    small_mm(n, n, n, Sp_, n, 0, Spi_, n, 0, tmp_, n);
+    ns_residual_kernel<<<1, 256, 0, s_>>>(n, tmp_, lam_);
+  }
+  auto info = fetch(ival_, 1);
   if (info[0] != 0) throw Unstable("A - B is not positive definite in the subspace");
-  if (info[1] != 0) throw Unstable("S is not positive definite in the subspace");
-  small_trinv(n, L_, Li_, s_);
-  small_trinv(n, Ls_, Lsi_, s_);
-  // Spi = Lsi^T Lsi
-  small_mm(n, n, n, Lsi_, n, 1, Lsi_, n, 0, Spi_, n);
-  // tmp = Spi L ; K = tmp^T Ap tmp
+  if (c_.order >= 2) {
+    auto res = fetch(lam_, 1);
+    if (!(res[0] < 1e-13)) {
+      small_cholesky(n, Sp_, Ls_, ival_ + 1, s_);
+      auto inf2 = fetch(ival_ + 1, 1);
+      if (inf2[0] != 0) throw Unstable("S is not positive definite in the subspace");
+      small_trinv(n, Ls_, Lsi_, s_);
+      small_mm(n, n, n, Lsi_, n, 1, Lsi_, n, 0, Spi_, n);
+    }
+  }
+  // Mt = Sp^-1 L ; K = Mt^T Ap Mt
   small_mm(n, n, n, Spi_, n, 0, L_, n, 0, tmp_, n);
   small_mm(n, n, n, Ap_, n, 0, tmp_, n, 0, tmp2_, n);
   small_mm(n, n, n, tmp_, n, 1, tmp2_, n, 0, K_, n);
   symmetrize_kernel<<<gridn((long)n * n), kB, 0, s_>>>(K_, n);
-  small_syev(n, K_, th2_, Zk_, s_, eigscr_);
-  auto th2 = fetch(th2_, n);
-  if (th2[0] <= 0) throw Unstable("A + B is not positive definite in the subspace");
-  std::vector<double> th(n);
-  for (int j = 0; j < n; ++j) th[j] = std::sqrt(th2[j]);
+  // eigenpairs of K nearest omega0^2 (candidate roots of the window)
+  const int p = std::min(n, std::min(64, std::max(2 * m_ + 4, nr_ + 8)));
+  const int q = partial_syev(n, K_, w0_ * w0_, p, th2_, Zk_, eigscr_, s_);
+  auto th2 = fetch(th2_, q);
+  for (int j = 0; j < q; ++j)
+    if (!(th2[j] > 0)) throw Unstable("A + B is not positive definite in the subspace");
+  std::vector<double> th(q);
+  for (int j = 0; j < q; ++j) th[j] = std::sqrt(th2[j]);
   upload(th_, th);
-  // us = tmp Zk / sqrt(th),  ws = Li^T Zk sqrt(th)
-  small_mm(n, n, n, tmp_, n, 0, Zk_, n, 0, us_, n);
-  scale_cols_kernel<<<gridn((long)n * n), kB, 0, s_>>>(us_, n, n, n, th_, 3);
-  small_mm(n, n, n, Li_, n, 1, Zk_, n, 0, ws_, n);
-  scale_cols_kernel<<<gridn((long)n * n), kB, 0, s_>>>(ws_, n, n, n, th_, 2);
-  // products of the Ritz halves: PU = P0 us, MW = P1 ws, SU = PS us, SW = PS ws  ([n][N])
-  expand(n, n, us_, n, P0_, RU_);
-  expand(n, n, ws_, n, P1_, RW_);
-  expand(n, n, us_, n, PS_, RSU_);
-  expand(n, n, ws_, n, PS_, RSW_);
-  residual_norms_kernel<<<n, kB, 0, s_>>>(N_, n, th_, w0_, RU_, RW_, RSU_, RSW_, stats_);
-  // |y|^2 = (|us|^2 + |ws|^2)/2 (Q orthonormal): column norms of the coefficient matrices
-  auto st = fetch(stats_, 2 * (size_t)n);
-  auto us = fetch(us_, (size_t)n * n);
-  auto ws = fetch(ws_, (size_t)n * n);
+  rld_ = q;
+  // us = Mt Z / sqrt(theta),  ws = sqrt(theta) L^-T Z
+  small_mm(n, q, n, tmp_, n, 0, Zk_, p, 0, us_, q);
+  scale_cols_kernel<<<gridn((long)n * q), kB, 0, s_>>>(us_, n, q, q, th_, 3);
+  copy_cols_kernel<<<gridn((long)n * q), kB, 0, s_>>>(n, q, Zk_, p, ws_, q);
+  small_trsm_lt(n, L_, q, ws_, s_);
+  scale_cols_kernel<<<gridn((long)n * q), kB, 0, s_>>>(ws_, n, q, q, th_, 2);
+  // products of the Ritz halves: PU = P0 us, MW = P1 ws, SU = PS us, SW = PS ws  ([q][N])
+  expand(q, n, us_, q, P0_, RU_);
+  expand(q, n, ws_, q, P1_, RW_);
+  expand(q, n, us_, q, PS_, RSU_);
+  expand(q, n, ws_, q, PS_, RSW_);
+  residual_norms_kernel<<<q, kB, 0, s_>>>(N_, q, th_, w0_, RU_, RW_, RSU_, RSW_, stats_);
+  coeff_norms_kernel<<<(q + 63) / 64, 64, 0, s_>>>(n, q, us_, ws_, stats_ + 2 * q);
+  auto st = fetch(stats_, 3 * (size_t)q);
   Ritz R;
   R.th = th;
-  R.rn.resize(n);
-  R.fold.resize(n);
-  for (int j = 0; j < n; ++j) {
-    double y2 = 0.0;
-    for (int p = 0; p < n; ++p) y2 += us[(size_t)p * n + j] * us[(size_t)p * n + j] + ws[(size_t)p * n + j] * ws[(size_t)p * n + j];
-    y2 *= 0.5;
+  R.rn.resize(q);
+  R.fold.resize(q);
+  for (int j = 0; j < q; ++j) {
+    const double y2 = 0.5 * st[2 * q + j];   // |y|^2 = (|u|^2 + |w|^2)/2, Q orthonormal
     R.rn[j] = std::sqrt(0.5 * st[j] / y2);
-    R.fold[j] = 0.5 * st[n + j] / y2;
+    R.fold[j] = 0.5 * st[q + j] / y2;
   }
   return R;
 }
@@ -763,7 +821,7 @@ void Solver::run(double* energies, double* vectors, double* osc, pp_solve_info* 
       axpy_cols_kernel<<<gridn((long)nb_ * knew), kB, 0, s_>>>(nb_, knew, kmax_, alpha_, cdy_, kmax_, cy_);
     }
     R = rayleigh_ritz();
-    const int n = nb_;
+    const int n = (int)R.th.size();
     std::vector<int> order(n);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return R.fold[a] < R.fold[b]; });
@@ -795,8 +853,8 @@ void Solver::run(double* energies, double* vectors, double* osc, pp_solve_info* 
   upload(sel_, sel);
   const int n = nb_;
   // coefficient columns of the selected roots: us_sel, ws_sel ([n][r], ld r)
-  gather_cols_kernel<<<gridn((long)n * r), kB, 0, s_>>>(n, r, sel_, us_, n, c1_, r, 0);
-  gather_cols_kernel<<<gridn((long)n * r), kB, 0, s_>>>(n, r, sel_, ws_, n, c2_, r, 0);
+  gather_cols_kernel<<<gridn((long)n * r), kB, 0, s_>>>(n, r, sel_, us_, rld_, c1_, r, 0);
+  gather_cols_kernel<<<gridn((long)n * r), kB, 0, s_>>>(n, r, sel_, ws_, rld_, c2_, r, 0);
   expand(r, n, c1_, r, Q_, T1_);
   expand(r, n, c2_, r, Q_, T2_);
   if (vectors) {
