@@ -134,6 +134,18 @@ pp_status pp_sigma(pp_handle* h, int32_t order, int32_t m, const double* X, doub
 pp_status pp_window_solve(pp_handle* h, double omega0, int32_t n_roots, double* energies, double* vectors,
                           double* osc, pp_solve_info* info);
 
+/* Several windows of the same system in one call: the windows are solved
+ * concurrently (one host thread and one HIP stream each for the subspace work) and
+ * their products are merged into shared product passes, so one pass of the
+ * amplitude contraction serves every window.  omega0[n_windows]; outputs are
+ * window-major: energies[n_windows][n_roots], vectors[n_windows][n_roots][2][n_occ][n_vir]
+ * (nullable), osc[n_windows][n_roots] (nullable), info[n_windows] (nullable; the
+ * product time/flops fields hold the totals of the whole call).  Each window's
+ * result equals its pp_window_solve result within the solver tolerance.
+ * PP_ENOTCONV if any window stopped at max_cycles (all outputs written). */
+pp_status pp_window_solve_batch(pp_handle* h, int32_t n_windows, const double* omega0, int32_t n_roots,
+                                double* energies, double* vectors, double* osc, pp_solve_info* info);
+
 /* Cumulative device-side accounting of the handle's products (every pp_sigma
  * and every product inside pp_window_solve), timed with HIP events on the
  * handle's stream.  "hhat" is the dominant contraction H = tau G of the

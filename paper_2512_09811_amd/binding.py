@@ -73,6 +73,8 @@ def lib() -> C.CDLL:
         L.pp_sigma.restype = C.c_int
         L.pp_window_solve.argtypes = [vp, dbl, i32, vp, vp, vp, C.POINTER(pp_solve_info)]
         L.pp_window_solve.restype = C.c_int
+        L.pp_window_solve_batch.argtypes = [vp, i32, vp, i32, vp, vp, vp, vp]
+        L.pp_window_solve_batch.restype = C.c_int
         L.pp_get_stats.argtypes = [vp, C.POINTER(pp_stats)]
         L.pp_get_stats.restype = C.c_int
         L.pp_reset_stats.argtypes = [vp]
@@ -223,6 +225,30 @@ class Handle:
 
     def reset_stats(self):
         _check(lib().pp_reset_stats(self.h), self.h)
+
+    def window_solve_batch(self, omegas, n_roots: int, vectors: bool = True, osc: bool = True,
+                           allow_unconverged: bool = False):
+        """All windows in one call; returns (energies [w][r], vectors [w][r][2][N] or None,
+        osc [w][r] or None, list of info dicts)."""
+        om = np.ascontiguousarray(omegas, dtype=np.float64)
+        nw = len(om)
+        e = np.empty((nw, n_roots))
+        vec = np.empty((nw, n_roots, 2, self.N)) if vectors else None
+        f = np.empty((nw, n_roots)) if osc else None
+        infos = (pp_solve_info * nw)()
+        st = lib().pp_window_solve_batch(self.h, nw, om.ctypes.data, n_roots, e.ctypes.data,
+                                         vec.ctypes.data if vec is not None else None,
+                                         f.ctypes.data if f is not None else None, infos)
+        if not (st == PP_ENOTCONV and allow_unconverged):
+            _check(st, self.h)
+        out = []
+        for w in range(nw):
+            info = infos[w]
+            out.append(dict(cycles=info.cycles, basis=info.basis, products=info.products, seconds=info.seconds,
+                            sigma_seconds=info.sigma_seconds, sigma_flops=info.sigma_flops,
+                            residual=np.array(info.residual[:n_roots]),
+                            converged=np.array(info.converged[:n_roots]), status=st))
+        return e, vec, f, out
 
     def mp2_energy(self) -> float:
         return lib().pp_mp2_energy(self.h)

@@ -197,6 +197,29 @@ pp_status pp_window_solve(pp_handle* h, double omega0, int32_t n_roots, double* 
   });
 }
 
+pp_status pp_window_solve_batch(pp_handle* h, int32_t n_windows, const double* omega0, int32_t n_roots,
+                                double* energies, double* vectors, double* osc, pp_solve_info* info) {
+  if (!h || !h->ctx) return PP_EINVAL;
+  return guarded(&h->err, [&] {
+    if (n_windows < 1 || n_windows > 64) throw ppw::InvalidArg("n_windows must be in 1..64");
+    if (!omega0 || !energies) throw ppw::InvalidArg("omega0 and energies must not be NULL");
+    for (int w = 0; w < n_windows; ++w)
+      if (!std::isfinite(omega0[w])) throw ppw::InvalidArg("omega0 must be finite");
+    if (n_roots < 1 || n_roots > PP_MAX_ROOTS || n_roots > h->ctx->N) throw ppw::InvalidArg("n_roots out of range");
+    if (osc && !h->ctx->dip) throw ppw::InvalidArg("oscillator strengths need dipole integrals at setup");
+    ppw::SolveOptions so;
+    so.precision = h->opt.precision;
+    so.tol = h->opt.tol;
+    so.block = h->opt.block;
+    so.krylov_steps = h->opt.krylov_steps;
+    so.max_basis = h->opt.max_basis;
+    so.max_cycles = h->opt.max_cycles;
+    so.d_clamp = h->opt.d_clamp;
+    so.seed = h->opt.seed;
+    ppw::window_solve_many(*h->ctx, so, n_windows, omega0, n_roots, energies, vectors, osc, info);
+  });
+}
+
 pp_status pp_get_stats(pp_handle* h, pp_stats* st) {
   if (!h || !h->ctx || !st) return PP_EINVAL;
   return guarded(&h->err, [&] {

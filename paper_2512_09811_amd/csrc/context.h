@@ -100,7 +100,7 @@ class EventLog {
     for (auto e : pool_) (void)hipEventDestroy(e);
   }
   int start(hipStream_t s) {
-    Rec r{get(), get(), 0, 0.0};
+    Rec r{get(), get(), -1, 0.0};
     PPW_HIP(hipEventRecord(r.a, s));
     recs_.push_back(r);
     return (int)recs_.size() - 1;
@@ -110,12 +110,15 @@ class EventLog {
     PPW_HIP(hipEventRecord(recs_[i].b, s));
   }
   // synchronizes on the recorded events and adds elapsed seconds per kind
+  // (records whose stop was never reached, after an error, are discarded)
   void resolve(double* seconds_by_kind, int nkinds) {
     for (auto& r : recs_) {
-      PPW_HIP(hipEventSynchronize(r.b));
-      float ms = 0.f;
-      PPW_HIP(hipEventElapsedTime(&ms, r.a, r.b));
-      if (r.kind >= 0 && r.kind < nkinds) seconds_by_kind[r.kind] += 1e-3 * ms;
+      if (r.kind >= 0 && r.kind < nkinds) {
+        PPW_HIP(hipEventSynchronize(r.b));
+        float ms = 0.f;
+        PPW_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+        seconds_by_kind[r.kind] += 1e-3 * ms;
+      }
       pool_.push_back(r.a);
       pool_.push_back(r.b);
     }
@@ -209,6 +212,9 @@ void sigma_core(Context& c, int order, int k, const double* V, double* AV, doubl
 
 // Same products with the contractions on FP32 matrix cores (V and outputs FP64).
 void sigma_core_f32(Context& c, int order, int k, const double* V, double* AV, double* BV, double* SV);
+
+// Grows the product workspace to k vectors ahead of time (no allocation in the loop).
+void sigma_reserve(Context& c, int k, int precision);
 
 // Algorithmic flops of one product pass over k vectors at the given order.
 double sigma_flops(const Context& c, int order, int k);

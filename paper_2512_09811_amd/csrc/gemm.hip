@@ -50,12 +50,16 @@ struct Mfma<float> {
 
 constexpr int kThreads = 256;
 
-__device__ __forceinline__ void tile_coords(int bid, int tiles_m, int tiles_n, int& tm, int& tn) {
-  const int ntiles = tiles_m * tiles_n;
-  // XCD-aware remap: hardware dispatches consecutive ids round-robin over 8 XCDs.
-  int id = bid;
-  const int per = ntiles / 8;
-  if (per > 0 && bid < per * 8) id = (bid % 8) * per + bid / 8;
+// XCD-aware remap of a flattened workgroup id: the hardware dispatches consecutive
+// ids round-robin over the 8 XCDs, so id -> (id % 8) * per + id / 8 gives each XCD a
+// contiguous range of (batch, tile) work that shares operands in its own L2.
+__device__ __forceinline__ long xcd_remap(long bid, long total) {
+  const long per = total / 8;
+  if (per > 0 && bid < per * 8) return (bid % 8) * per + bid / 8;
+  return bid;
+}
+
+__device__ __forceinline__ void tile_coords(int id, int tiles_m, int tiles_n, int& tm, int& tn) {
   // grouped ordering: bands of GROUP tile-rows walked column by column
   constexpr int GROUP = 8;
   const int in_group = GROUP * tiles_n;
@@ -102,12 +106,14 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_kernel(GemmDesc d, T alpha, 
 
   const int tiles_m = (d.M + BM - 1) / BM;
   const int tiles_n = (d.N + BN - 1) / BN;
+  const long ntiles = (long)tiles_m * tiles_n;
+  const long flat = xcd_remap(blockIdx.x, (long)gridDim.x);
+  const int batch = (int)(flat / ntiles);
   int tm, tn;
-  tile_coords(blockIdx.x, tiles_m, tiles_n, tm, tn);
+  tile_coords((int)(flat % ntiles), tiles_m, tiles_n, tm, tn);
   const int m0 = tm * BM, n0 = tn * BN;
-  const int batch = blockIdx.y;
   const int b1 = batch / d.nb2, b2 = batch % d.nb2;
-  const int split = blockIdx.z;
+  const int split = blockIdx.y;
 
   const T* Ab = A + b1 * d.sA1 + b2 * d.sA2;
   const T* Bb = B + b1 * d.sB1 + b2 * d.sB2;
@@ -242,11 +248,14 @@ __global__ void splitk_reduce_kernel(GemmDesc d, T alpha, T beta, const T* __res
   }
 }
 
+inline bool ntiles_total_exceeds(long n) { return n <= 0 || n > 2147483647L; }
+
 template <typename T, int BM, int BN, int BK, bool AK, bool BKC, int TAG>
 void launch(const GemmDesc& d, T alpha, const T* A, const T* B, T beta, T* C, hipStream_t s, Workspace ws) {
   const int tiles_m = (d.M + BM - 1) / BM, tiles_n = (d.N + BN - 1) / BN;
   const long nbatch = (long)d.nb1 * d.nb2;
-  if (nbatch > 65535) throw InvalidArg("gemm: batch count exceeds 65535");
+  if (ntiles_total_exceeds((long)((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN) * nbatch))
+    throw InvalidArg("gemm: too many workgroups");
   // per-tile element offsets are 32-bit inside the kernel
   if ((double)d.lda * std::max(BM, BK) + d.K >= 2147483647.0 || (double)d.ldb * std::max(BN, BK) + d.K >= 2147483647.0)
     throw InvalidArg("gemm: leading dimension too large for 32-bit tile offsets");
@@ -264,7 +273,7 @@ void launch(const GemmDesc& d, T alpha, const T* A, const T* B, T beta, T* C, hi
     want = std::min<long>(want, 256);
     if (want >= 2) splitk = (int)want;
   }
-  dim3 grid((unsigned)ntiles, (unsigned)nbatch, (unsigned)splitk);
+  dim3 grid((unsigned)(ntiles * nbatch), (unsigned)splitk, 1);
   if (splitk == 1) {
     gemm_kernel<T, BM, BN, BK, AK, BKC, TAG><<<grid, kThreads, 0, s>>>(d, alpha, A, B, beta, C, nullptr, 1);
     PPW_LAUNCH_CHECK();

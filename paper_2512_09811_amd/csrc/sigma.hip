@@ -261,6 +261,11 @@ void grow_workspace(Context& c, int k) {
 
 }  // namespace
 
+void sigma_reserve(Context& c, int k, int precision) {
+  (void)precision;
+  if (c.order >= 1) grow_workspace(c, k);
+}
+
 void sigma_core(Context& c, int order, int k, const double* V, double* AV, double* BV, double* SV) {
   if (order > c.order) throw InvalidArg("requested order exceeds the setup order");
   if (k <= 0) return;

@@ -25,6 +25,11 @@
 // folded quotient) and eigenvalue lists that decide which directions to keep.
 #include <algorithm>
 #include <chrono>
+#include <condition_variable>
+#include <exception>
+#include <memory>
+#include <mutex>
+#include <thread>
 #include <cmath>
 #include <numeric>
 #include <random>
@@ -351,20 +356,126 @@ GemmDesc gd(int M, int N, int K, int tA, long lda, int tB, long ldb, long ldc) {
 }
 
 // ---------------------------------------------------------------------------
+// Merges the product requests of concurrently running window solves of one system
+// into a single product pass.  Each window thread submits its block (recorded as
+// ready on its own stream) and blocks; when every active window has submitted, the
+// last one runs the pass on the system's stream and the results are copied back,
+// with a completion event per request.  Requests are served in window order, so the
+// batch composition (and therefore every rounding) is a deterministic function of
+// the inputs.
+class ProductBatcher {
+ public:
+  struct Req {
+    int id = 0;
+    int k = 0;
+    const double* V = nullptr;
+    double *AV = nullptr, *BV = nullptr, *SV = nullptr;
+    hipEvent_t ready = nullptr, done = nullptr;
+    bool served = false;
+    std::exception_ptr err;
+  };
+  ProductBatcher(Context& c, int active, int precision) : c_(c), active_(active), prec_(precision) {}
+  ~ProductBatcher() {
+    for (void* q : bufs_) c_.arena.free(q);
+  }
+  void reserve(int ktot) {
+    const size_t n = (size_t)ktot * c_.N;
+    V_ = c_.arena.alloc<double>(n, "batch V");
+    AV_ = c_.arena.alloc<double>(n, "batch AV");
+    BV_ = c_.arena.alloc<double>(n, "batch BV");
+    SV_ = c_.arena.alloc<double>(n, "batch SV");
+    bufs_ = {V_, AV_, BV_, SV_};
+    cap_ = ktot;
+    sigma_reserve(c_, ktot, prec_);
+  }
+  void multiply(Req& r) {
+    std::unique_lock<std::mutex> lk(mu_);
+    r.served = false;
+    pending_.push_back(&r);
+    if ((int)pending_.size() >= active_)
+      serve();
+    else
+      cv_.wait(lk, [&] { return r.served; });
+    if (r.err) std::rethrow_exception(r.err);
+  }
+  void leave() {
+    std::unique_lock<std::mutex> lk(mu_);
+    --active_;
+    if (active_ > 0 && (int)pending_.size() >= active_) serve();
+  }
+
+ private:
+  void serve() {
+    std::exception_ptr err;
+    std::sort(pending_.begin(), pending_.end(), [](const Req* a, const Req* b) { return a->id < b->id; });
+    try {
+      int kt = 0;
+      for (auto* r : pending_) kt += r->k;
+      if (kt > cap_) throw InvalidArg("product batch exceeds its reserved size");
+      hipStream_t s = c_.stream;
+      const long N = c_.N;
+      long off = 0;
+      for (auto* r : pending_) {
+        PPW_HIP(hipStreamWaitEvent(s, r->ready, 0));
+        PPW_HIP(hipMemcpyAsync(V_ + off * N, r->V, sizeof(double) * r->k * N, hipMemcpyDeviceToDevice, s));
+        off += r->k;
+      }
+      if (prec_ == 1)
+        sigma_core_f32(c_, c_.order, kt, V_, AV_, BV_, SV_);
+      else
+        sigma_core(c_, c_.order, kt, V_, AV_, BV_, SV_);
+      off = 0;
+      for (auto* r : pending_) {
+        const size_t b = sizeof(double) * r->k * N;
+        PPW_HIP(hipMemcpyAsync(r->AV, AV_ + off * N, b, hipMemcpyDeviceToDevice, s));
+        PPW_HIP(hipMemcpyAsync(r->BV, BV_ + off * N, b, hipMemcpyDeviceToDevice, s));
+        PPW_HIP(hipMemcpyAsync(r->SV, SV_ + off * N, b, hipMemcpyDeviceToDevice, s));
+        PPW_HIP(hipEventRecord(r->done, s));
+        off += r->k;
+      }
+    } catch (...) {
+      err = std::current_exception();
+    }
+    for (auto* r : pending_) {
+      r->err = err;
+      r->served = true;
+    }
+    pending_.clear();
+    cv_.notify_all();
+  }
+  Context& c_;
+  int active_;
+  int prec_;
+  std::mutex mu_;
+  std::condition_variable cv_;
+  std::vector<Req*> pending_;
+  double *V_ = nullptr, *AV_ = nullptr, *BV_ = nullptr, *SV_ = nullptr;
+  std::vector<void*> bufs_;
+  int cap_ = 0;
+};
+
 class Solver {
  public:
-  Solver(Context& c, const SolveOptions& o, double w0, int nroots)
-      : c_(c), opt_(o), w0_(w0), nr_(nroots), s_(c.stream), N_(c.N) {
+  Solver(Context& c, const SolveOptions& o, double w0, int nroots, ProductBatcher* pb, int id)
+      : c_(c), opt_(o), w0_(w0), nr_(nroots), N_(c.N), pb_(pb), id_(id) {
     m_ = o.block > 0 ? o.block : nroots + std::max(2, nroots / 2);
     m_ = (int)std::min<long>(m_, N_);
     nbmax_ = (int)std::min<long>(o.max_basis > 0 ? o.max_basis : 400, N_);
     nbmax_ = std::max(nbmax_, std::min<int>((int)N_, 2 * m_));
     kmax_ = 2 * m_;  // new vectors per extension (X and Y halves of a block)
+    PPW_HIP(hipStreamCreateWithFlags(&s_, hipStreamNonBlocking));
+    PPW_HIP(hipEventCreateWithFlags(&ev_ready_, hipEventDisableTiming));
+    PPW_HIP(hipEventCreateWithFlags(&ev_done_, hipEventDisableTiming));
     alloc();
   }
   ~Solver() {
+    if (s_) (void)hipStreamSynchronize(s_);
     for (void* p : owned_) c_.arena.free(p);
+    if (ev_ready_) (void)hipEventDestroy(ev_ready_);
+    if (ev_done_) (void)hipEventDestroy(ev_done_);
+    if (s_) (void)hipStreamDestroy(s_);
   }
+  int kmax() const { return kmax_; }
 
   void run(double* energies, double* vectors, double* osc, pp_solve_info* info);
 
@@ -373,8 +484,12 @@ class Solver {
   SolveOptions opt_;
   double w0_;
   int nr_, m_, nbmax_, kmax_;
-  hipStream_t s_;
+  hipStream_t s_ = nullptr;
   long N_;
+  ProductBatcher* pb_;
+  int id_;
+  hipEvent_t ev_ready_ = nullptr, ev_done_ = nullptr;
+  Workspace wsp_;
   int nb_ = 0;
   int rld_ = 1;  // columns (leading dimension) of the current Ritz coefficient matrices us_/ws_
   std::vector<void*> owned_;
@@ -467,11 +582,13 @@ class Solver {
     ival_ = get<int>(4, "info");
     sel_ = get<int>(std::max(kmax_, nbmax_), "sel");
     noise_ = get<double>((size_t)2 * m_ * N_, "noise");
+    wsp_.bytes = (size_t)32 << 20;
+    wsp_.ptr = get<char>(wsp_.bytes, "solver split-K workspace");
     PPW_HIP(hipMemsetAsync(Q_, 0, sizeof(double) * bN, s_));
   }
 
   void gemm(const GemmDesc& d, double a, const double* A, const double* B, double b, double* C) {
-    gemm_f64(d, a, A, B, b, C, s_, c_.ws);
+    gemm_f64(d, a, A, B, b, C, s_, wsp_);
   }
   template <typename T>
   std::vector<T> fetch(const T* p, size_t n) {
@@ -506,11 +623,21 @@ class Solver {
     gemm(gd(m, n, k, tA, lda, tB, ldb, ldc), alpha, A, B, beta, C);
   }
 
+  // A, B, S products of k orthonormal vectors X (device, [k][N]) into AV_, BV_, SV_,
+  // merged with the other windows' requests by the batcher
   void products(int k, const double* X) {
-    if (opt_.precision == 1)
-      sigma_core_f32(c_, c_.order, k, X, AV_, BV_, SV_);
-    else
-      sigma_core(c_, c_.order, k, X, AV_, BV_, SV_);
+    ProductBatcher::Req r;
+    r.id = id_;
+    r.k = k;
+    r.V = X;
+    r.AV = AV_;
+    r.BV = BV_;
+    r.SV = SV_;
+    r.ready = ev_ready_;
+    r.done = ev_done_;
+    PPW_HIP(hipEventRecord(ev_ready_, s_));
+    pb_->multiply(r);
+    PPW_HIP(hipStreamWaitEvent(s_, ev_done_, 0));
     products_ += k;
   }
 
@@ -734,8 +861,6 @@ Solver::Ritz Solver::rayleigh_ritz() {
 
 void Solver::run(double* energies, double* vectors, double* osc, pp_solve_info* info) {
   const auto t0 = std::chrono::steady_clock::now();
-  c_.resolve_stats();
-  const double sig0 = c_.stats.seconds, flop0 = c_.stats.flops;
   // start block: m top-half pairs with the smallest |A_ii - w0 S_ii|
   auto dA = fetch(c_.dA, N_);
   auto dS = fetch(c_.dS, N_);
@@ -872,7 +997,6 @@ void Solver::run(double* energies, double* vectors, double* osc, pp_solve_info* 
     for (int q = 0; q < r; ++q) osc[q] = f[q];
   }
   PPW_HIP(hipStreamSynchronize(s_));
-  c_.resolve_stats();
   if (info) {
     info->cycles = cycle;
     info->basis = nb_;
@@ -883,19 +1007,69 @@ void Solver::run(double* energies, double* vectors, double* osc, pp_solve_info* 
       info->converged[q] = R.rn[sel[q]] <= opt_.tol ? 1 : 0;
     }
     info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    info->sigma_seconds = c_.stats.seconds - sig0;
-    info->sigma_flops = c_.stats.flops - flop0;
   }
   if (!converged) throw NotConverged("window solve reached max_cycles before every root met the tolerance");
 }
 
 }  // namespace
 
+void window_solve_many(Context& c, const SolveOptions& opt, int nw, const double* omega0, int n_roots,
+                       double* energies, double* vectors, double* osc, pp_solve_info* info) {
+  PPW_HIP(hipSetDevice(c.device));
+  if (nw < 1) return;
+  c.resolve_stats();
+  const double sig0 = c.stats.seconds, flop0 = c.stats.flops;
+  ProductBatcher pb(c, nw, opt.precision);
+  std::vector<std::unique_ptr<Solver>> sv;
+  int ktot = 0;
+  for (int w = 0; w < nw; ++w) {
+    sv.emplace_back(new Solver(c, opt, omega0[w], n_roots, &pb, w));
+    ktot += sv.back()->kmax();
+  }
+  pb.reserve(ktot);
+  PPW_HIP(hipStreamSynchronize(c.stream));
+  std::vector<std::exception_ptr> errs(nw);
+  auto work = [&](int w) {
+    try {
+      PPW_HIP(hipSetDevice(c.device));
+      const size_t N = (size_t)c.N;
+      sv[w]->run(energies + (size_t)w * n_roots, vectors ? vectors + (size_t)w * n_roots * 2 * N : nullptr,
+                 osc ? osc + (size_t)w * n_roots : nullptr, info ? info + w : nullptr);
+    } catch (...) {
+      errs[w] = std::current_exception();
+    }
+    pb.leave();
+  };
+  if (nw == 1) {
+    work(0);
+  } else {
+    std::vector<std::thread> th;
+    for (int w = 0; w < nw; ++w) th.emplace_back(work, w);
+    for (auto& t : th) t.join();
+  }
+  PPW_HIP(hipStreamSynchronize(c.stream));
+  sv.clear();
+  c.resolve_stats();
+  if (info)
+    for (int w = 0; w < nw; ++w) {
+      info[w].sigma_seconds = c.stats.seconds - sig0;
+      info[w].sigma_flops = c.stats.flops - flop0;
+    }
+  std::exception_ptr notconv;
+  for (auto& e : errs) {
+    if (!e) continue;
+    try {
+      std::rethrow_exception(e);
+    } catch (const NotConverged&) {
+      notconv = e;
+    }
+  }
+  if (notconv) std::rethrow_exception(notconv);
+}
+
 void window_solve(Context& c, const SolveOptions& opt, double omega0, int n_roots, double* energies,
                   double* vectors, double* osc, pp_solve_info* info) {
-  PPW_HIP(hipSetDevice(c.device));
-  Solver sv(c, opt, omega0, n_roots);
-  sv.run(energies, vectors, osc, info);
+  window_solve_many(c, opt, 1, &omega0, n_roots, energies, vectors, osc, info);
 }
 
 }  // namespace ppw

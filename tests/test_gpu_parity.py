@@ -133,3 +133,18 @@ def test_error_paths(P):
         e, vec, f, info = h.window_solve(0.5, 6, allow_unconverged=True)
         assert info["status"] == P.PP_ENOTCONV
         assert np.all(np.isfinite(e))
+
+
+def test_window_batch_matches_single_and_oracle(P):
+    """Windows solved together (shared product passes) agree with the oracle and with solo solves."""
+    sys = gen(7, 12, 40, 100)
+    omegas = [0.45, 0.8, 1.1, 1.6]
+    with P.Handle.from_system(sys, order=2) as h:
+        eb, vb, fb, infos = h.window_solve_batch(omegas, 6)
+        solo = [h.window_solve(w, 6) for w in omegas]
+    for k, w in enumerate(omegas):
+        _check_window(sys, 2, w, 6, eb[k], vb[k], fb[k], infos[k])
+        np.testing.assert_allclose(eb[k], solo[k][0], rtol=0, atol=1e-10)
+    with P.Handle.from_system(sys, order=2) as h:
+        eb2, _, fb2, _ = h.window_solve_batch(omegas, 6)
+    assert np.array_equal(eb, eb2) and np.array_equal(fb, fb2)
