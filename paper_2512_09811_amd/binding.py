@@ -61,6 +61,15 @@ def lib() -> C.CDLL:
     """The loaded library (raises if it has not been built)."""
     global _lib
     if _lib is None:
+        # torch (used by callers for device memory and streams) ships its own HIP and
+        # HSA runtimes; they must initialize before the system runtime this library
+        # links, or torch no longer finds the GPU.  Initialize torch's first when it is
+        # installed (on a machine without a GPU this is a no-op).
+        try:
+            import torch
+            torch.cuda.is_available()
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"libppwin.so not found at {LIB_PATH}: run __graft_entry__.build() first")
         L = C.CDLL(LIB_PATH)

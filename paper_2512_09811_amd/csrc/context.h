@@ -81,6 +81,7 @@ struct SetupParams {
 // Timing/flop accounting of product passes.
 struct SigmaStats {
   double flops = 0.0;       // algorithmic flops issued by product passes
+  double flops32 = 0.0;     // of which on the FP32 path
   double seconds = 0.0;     // device time of product passes (events)
   long vectors = 0;         // particle-hole vectors multiplied
   double hhat_flops = 0.0;  // flops of the amplitude-weighted contraction (dominant kernel)
@@ -180,6 +181,7 @@ struct Context {
   // product workspace (grown on demand)
   int kcap = 0;
   int kcap32 = 0;
+  int kcap_asm = 0;
   double *w_c = nullptr, *w_J = nullptr, *w_G = nullptr, *w_U = nullptr, *w_H = nullptr, *w_S = nullptr,
          *w_tau = nullptr, *w_P = nullptr;
   float *w32_V = nullptr, *w32_c = nullptr, *w32_J = nullptr, *w32_G = nullptr, *w32_U = nullptr,

@@ -220,6 +220,26 @@ Context* setup_context(const SetupParams& p) {
                   s);
     c->R = c->arena.alloc<double>((size_t)o * c->ns * X * v, "ring operand");
     build_ring_operand(c->Bov, c->Lam, o, v, X, c->R, s);
+    if (p.want_f32 && p.order >= 1) {
+      // FP32 copies of every operand of the reduced-precision product path
+      auto cp32 = [&](const double* src, size_t n, const char* w) {
+        float* d = c->arena.alloc<float>(n, w);
+        to_f32((long)n, src, d, s);
+        return d;
+      };
+      c->BovLam32 = cp32(c->BovLam, (size_t)c->ns * X * N, "B_ov fp32");
+      c->Boo32 = cp32(c->Boo, (size_t)X * o * o, "B_oo fp32");
+      c->Bvv32 = cp32(c->Bvv, (size_t)X * v * v, "B_vv fp32");
+      c->Boo_t32 = cp32(c->Boo_t, (size_t)o * o * X, "B_oo [i][j][P] fp32");
+      c->R32 = cp32(c->R, (size_t)o * c->ns * X * v, "ring operand fp32");
+      if (p.order >= 2) {
+        if (c->tau) c->tau32 = cp32(c->tau, (size_t)N * N, "amplitudes tau fp32");
+        c->Gv32 = cp32(c->Gv, (size_t)v * v, "Gv fp32");
+        c->Ev32 = cp32(c->Ev, (size_t)v * v, "Ev fp32");
+        c->Go32 = cp32(c->Go, (size_t)o * o, "Go fp32");
+        c->Eo32 = cp32(c->Eo, (size_t)o * o, "Eo fp32");
+      }
+    }
     PPW_HIP(hipStreamSynchronize(s));
     c->arena.free(exch);
     c->arena.free(coul);
@@ -233,77 +253,137 @@ Context* setup_context(const SetupParams& p) {
 
 namespace {
 
+template <typename T>
+T* regrow(Context& c, T*& p, size_t n, const char* w) {
+  if (p) c.arena.free(p);
+  p = c.arena.alloc<T>(n, w);
+  return p;
+}
+
+// FP64 buffers every product pass needs for the final (FP64) assembly
+void grow_assembly(Context& c, int k) {
+  if (k <= c.kcap_asm) return;
+  regrow(c, c.w_J, (size_t)k * c.N, "ws J");
+  regrow(c, c.w_P, (size_t)4 * k * c.N, "ws P");
+  c.kcap_asm = k;
+}
+
 void grow_workspace(Context& c, int k) {
+  grow_assembly(c, k);
   if (k <= c.kcap) return;
   const int o = c.o, v = c.v, X = c.naux;
   const long N = c.N;
-  auto re = [&](double*& p, size_t n, const char* w) {
-    if (p) c.arena.free(p);
-    p = c.arena.alloc<double>(n, w);
-  };
-  re(c.w_c, (size_t)X * k, "ws c");
-  re(c.w_J, (size_t)k * N, "ws J");
-  re(c.w_G, (size_t)k * X * N, "ws G");
-  re(c.w_U, (size_t)k * o * c.ns * X * o, "ws U");
-  re(c.w_P, (size_t)4 * k * N, "ws P");
+  regrow(c, c.w_c, (size_t)X * k, "ws c");
+  regrow(c, c.w_G, (size_t)k * X * N, "ws G");
+  regrow(c, c.w_U, (size_t)k * o * c.ns * X * o, "ws U");
   if (c.order >= 2) {
     const int ib = c.tau ? o : c.strip_rows;
-    re(c.w_H, (size_t)ib * v * k * X, "ws H");
+    regrow(c, c.w_H, (size_t)ib * v * k * X, "ws H");
     if (!c.tau) {
-      re(c.w_S, (size_t)c.strip_rows * v * N, "ws strip S");
-      re(c.w_tau, (size_t)c.strip_rows * v * N, "ws strip tau");
+      regrow(c, c.w_S, (size_t)c.strip_rows * v * N, "ws strip S");
+      regrow(c, c.w_tau, (size_t)c.strip_rows * v * N, "ws strip tau");
     }
   }
   c.kcap = k;
 }
 
-
-
-}  // namespace
-
-void sigma_reserve(Context& c, int k, int precision) {
-  (void)precision;
-  if (c.order >= 1) grow_workspace(c, k);
+void grow_workspace32(Context& c, int k) {
+  grow_assembly(c, k);
+  if (k <= c.kcap32) return;
+  const int o = c.o, v = c.v, X = c.naux;
+  const long N = c.N;
+  regrow(c, c.w32_V, (size_t)k * N, "ws32 V");
+  regrow(c, c.w32_AV, (size_t)k * N, "ws32 AV");
+  regrow(c, c.w32_BV, (size_t)k * N, "ws32 BV");
+  regrow(c, c.w32_J, (size_t)k * N, "ws32 J");
+  regrow(c, c.w32_P, (size_t)4 * k * N, "ws32 P");
+  regrow(c, c.w32_c, (size_t)X * k, "ws32 c");
+  regrow(c, c.w32_G, (size_t)k * X * N, "ws32 G");
+  regrow(c, c.w32_U, (size_t)k * o * c.ns * X * o, "ws32 U");
+  if (c.order >= 2) {
+    const int ib = c.tau32 ? o : c.strip_rows;
+    regrow(c, c.w32_H, (size_t)ib * v * k * X, "ws32 H");
+    if (!c.tau32) {
+      regrow(c, c.w32_S, (size_t)c.strip_rows * v * N, "ws32 strip S");
+      regrow(c, c.w32_tau, (size_t)c.strip_rows * v * N, "ws32 strip tau");
+    }
+  }
+  c.kcap32 = k;
 }
 
-void sigma_core(Context& c, int order, int k, const double* V, double* AV, double* BV, double* SV) {
-  if (order > c.order) throw InvalidArg("requested order exceeds the setup order");
-  if (k <= 0) return;
+template <typename T>
+void gemm_t(const GemmDesc& d, T a, const T* A, const T* B, T b, T* C, hipStream_t s, Workspace ws);
+template <>
+void gemm_t<double>(const GemmDesc& d, double a, const double* A, const double* B, double b, double* C,
+                    hipStream_t s, Workspace ws) {
+  gemm_f64(d, a, A, B, b, C, s, ws);
+}
+template <>
+void gemm_t<float>(const GemmDesc& d, float a, const float* A, const float* B, float b, float* C, hipStream_t s,
+                   Workspace ws) {
+  gemm_f32(d, a, A, B, b, C, s, ws);
+}
+template <typename T>
+void gemm_hhat_t(const GemmDesc& d, T a, const T* A, const T* B, T b, T* C, hipStream_t s, Workspace ws);
+template <>
+void gemm_hhat_t<double>(const GemmDesc& d, double a, const double* A, const double* B, double b, double* C,
+                         hipStream_t s, Workspace ws) {
+  gemm_f64_hhat(d, a, A, B, b, C, s, ws);
+}
+template <>
+void gemm_hhat_t<float>(const GemmDesc& d, float a, const float* A, const float* B, float b, float* C,
+                        hipStream_t s, Workspace ws) {
+  gemm_f32_hhat(d, a, A, B, b, C, s, ws);
+}
+inline void tau_strip_t(const double* S, int o, int v, int k0, int ib, const double* eo, const double* ev, double* tau,
+                        hipStream_t s) {
+  tau_strip(S, o, v, k0, ib, eo, ev, tau, nullptr, nullptr, nullptr, nullptr, s);
+}
+inline void tau_strip_t(const float* S, int o, int v, int k0, int ib, const double* eo, const double* ev, float* tau,
+                        hipStream_t s) {
+  tau_strip_f32(S, o, v, k0, ib, eo, ev, tau, s);
+}
+
+// Operands and workspace of one precision.
+template <typename T>
+struct Ops {
+  const T *Bov, *BovLam, *Boo, *Bvv, *Boo_t, *R, *tau, *Gv, *Ev, *Go, *Eo;
+  T *c, *G, *U, *H, *S, *tau_w;
+};
+
+Ops<double> ops64(Context& c) {
+  return Ops<double>{c.Bov, c.BovLam, c.Boo, c.Bvv, c.Boo_t, c.R, c.tau, c.Gv, c.Ev, c.Go, c.Eo,
+                     c.w_c, c.w_G, c.w_U, c.w_H, c.w_S, c.w_tau};
+}
+Ops<float> ops32(Context& c) {
+  return Ops<float>{c.BovLam32, c.BovLam32, c.Boo32, c.Bvv32, c.Boo_t32, c.R32, c.tau32, c.Gv32, c.Ev32, c.Go32,
+                    c.Eo32, c.w32_c, c.w32_G, c.w32_U, c.w32_H, c.w32_S, c.w32_tau};
+}
+
+// Every contraction of the product (see the file comment): AV <- -K_A(V) [+0],
+// BV <- -K_B(V) - ring terms + ladder/ring-K terms, J, P1..P4 (delta-type
+// intermediates).  The diagonal term and the final combination are done in FP64
+// by sigma_assemble.
+template <typename T>
+void contract(Context& c, const Ops<T>& t, int order, int k, const T* V, T* AV, T* BV, T* J, T* P1, T* P2, T* P3,
+              T* P4) {
   hipStream_t s = c.stream;
   const int o = c.o, v = c.v, X = c.naux;
   const long N = c.N;
-  if (order == 0) {
-    sigma_assemble(o, v, k, 0, c.eps_o, c.eps_v, V, nullptr, nullptr, nullptr, nullptr, nullptr, AV, BV, SV, s);
-    return;
-  }
-  grow_workspace(c, k);
-  if (c.events.pending() > 4096) c.resolve_stats();
-  const int ev_pass = c.events.start(s);
-  double* cP = c.w_c;
-  double* J = c.w_J;
-  double* G = c.w_G;
-  double* U = c.w_U;
-  double* P1 = c.w_P;
-  double* P2 = P1 + (size_t)k * N;
-  double* P3 = P2 + (size_t)k * N;
-  double* P4 = P3 + (size_t)k * N;
-
+  const T one = T(1), zero = T(0), mone = T(-1);
   // J: c[P][q] = sum_ia Bov[P][ia] V[q][ia];  J[q][ia] = sum_P c[P][q] Bov[P][ia]
-  gemm_f64(gd(X, k, (int)N, 0, N, 1, N, k), 1.0, c.Bov, V, 0.0, cP, s, c.ws);
-  gemm_f64(gd(k, (int)N, X, 1, k, 0, N, N), 1.0, cP, c.Bov, 0.0, J, s, c.ws);
-
+  gemm_t<T>(gd(X, k, (int)N, 0, N, 1, N, k), one, t.Bov, V, zero, t.c, s, c.ws);
+  gemm_t<T>(gd(k, (int)N, X, 1, k, 0, N, N), one, t.c, t.Bov, zero, J, s, c.ws);
   // G1[q][P][j][d] = sum_b V[q][j][b] Bvv[P][b][d]
   {
     GemmDesc d = gd(o, v, v, 0, v, 0, v, v);
     d.nb1 = k;
     d.nb2 = X;
     d.sA1 = N;
-    d.sA2 = 0;
-    d.sB1 = 0;
     d.sB2 = (long)v * v;
     d.sC1 = (long)X * N;
     d.sC2 = N;
-    gemm_f64(d, 1.0, V, c.Bvv, 0.0, G, s, c.ws);
+    gemm_t<T>(d, one, V, t.Bvv, zero, t.G, s, c.ws);
   }
   // AV = -K_A(V) = -sum_P Boo_P G1_P
   {
@@ -314,24 +394,22 @@ void sigma_core(Context& c, int order, int k, const double* V, double* AV, doubl
     d.nb1 = k;
     d.sB1 = (long)X * N;
     d.sC1 = N;
-    gemm_f64(d, -1.0, c.Boo, G, 0.0, AV, s, c.ws);
+    gemm_t<T>(d, mone, t.Boo, t.G, zero, AV, s, c.ws);
   }
-  // U[(q,j)][(s,P,i)] = sum_b V[(q,j)][b] BovLam[(s,P,i)][b]
+  // U[(q,j)][(s,P,i)] = sum_b V[(q,j)][b] BovLam[(s,P,i)][b];  BV = -sum U R
   const int ns = order >= 2 ? 2 : 1;
-  const double* Rop = c.R;
   {
     const long Ucols = (long)ns * X * o;
-    gemm_f64(gd(k * o, (int)Ucols, v, 0, v, 1, v, Ucols), 1.0, V, c.BovLam, 0.0, U, s, c.ws);
-    // BV = -sum_(j,s,P) U[q][(j,s,P)][i] R[(j,s,P)][a]
+    gemm_t<T>(gd(k * o, (int)Ucols, v, 0, v, 1, v, Ucols), one, V, t.BovLam, zero, t.U, s, c.ws);
     if (ns == c.ns) {
       GemmDesc d = gd(o, v, o * ns * X, 1, o, 0, v, v);
       d.nb1 = k;
       d.sA1 = (long)o * Ucols;
       d.sC1 = N;
-      gemm_f64(d, -1.0, U, Rop, 0.0, BV, s, c.ws);
+      gemm_t<T>(d, mone, t.U, t.R, zero, BV, s, c.ws);
     } else {
-      // order-1 product on an order-2 handle: K_B(V) = sum_(j,P) U[q][(j,P)][i] Bov[P][j][a]
-      // with R[j][1][P][a] = Bov[P][j][a]: outer loop over j (stride 2 X v), inner P.
+      // first-order product on a second-order handle: K_B(V) = sum_(j,P) U[q][(j,P)][i] Bov[P][j][a],
+      // with R[j][1][P][a] = Bov[P][j][a] (outer loop over j, inner P)
       GemmDesc d = gd(o, v, X, 1, o, 0, v, v);
       d.KB = o;
       d.sAk = (long)X * o;
@@ -339,95 +417,149 @@ void sigma_core(Context& c, int order, int k, const double* V, double* AV, doubl
       d.nb1 = k;
       d.sA1 = (long)o * Ucols;
       d.sC1 = N;
-      gemm_f64(d, -1.0, U, Rop + (size_t)X * v, 0.0, BV, s, c.ws);
+      gemm_t<T>(d, mone, t.U, t.R + (size_t)X * v, zero, BV, s, c.ws);
     }
   }
-
-  if (order >= 2) {
-    // G_P = V Bvv_P - Boo_P V  (in place on G1)
+  if (order < 2) return;
+  // G_P = V Bvv_P - Boo_P V  (in place on G1)
+  {
+    GemmDesc d = gd(o, v, o, 0, o, 0, v, v);
+    d.nb1 = k;
+    d.nb2 = X;
+    d.sA2 = (long)o * o;
+    d.sB1 = N;
+    d.sC1 = (long)X * N;
+    d.sC2 = N;
+    gemm_t<T>(d, mone, t.Boo, V, one, t.G, s, c.ws);
+  }
+  const long kX = (long)k * X;
+  auto outputs = [&](const T* H, int i0, int ib) {
+    // BV[q][i][a] += sum_(c,P) H[(i,c)][(q,P)] Bvv[P][c][a]    rows i0..i0+ib-1
     {
-      GemmDesc d = gd(o, v, o, 0, o, 0, v, v);
+      GemmDesc d = gd(ib, v, X, 0, (long)v * kX, 0, (long)v * v, v);
+      d.KB = v;
+      d.sAk = kX;
+      d.sBk = v;
       d.nb1 = k;
-      d.nb2 = X;
-      d.sA1 = 0;
-      d.sA2 = (long)o * o;
-      d.sB1 = N;
-      d.sB2 = 0;
-      d.sC1 = (long)X * N;
-      d.sC2 = N;
-      gemm_f64(d, -1.0, c.Boo, V, 1.0, G, s, c.ws);
+      d.sA1 = X;
+      d.sC1 = N;
+      gemm_t<T>(d, one, H, t.Bvv, one, BV + (size_t)i0 * v, s, c.ws);
     }
-    const long kX = (long)k * X;
-    auto outputs = [&](const double* H, int i0, int ib) {
-      // BV[q][i][a] += sum_(c,P) H[(i,c)][(q,P)] Bvv[P][c][a]    for rows i0..i0+ib-1
-      {
-        GemmDesc d = gd(ib, v, X, 0, (long)v * kX, 0, (long)v * v, v);
-        d.KB = v;
-        d.sAk = kX;
-        d.sBk = v;
-        d.nb1 = k;
-        d.sA1 = X;
-        d.sC1 = N;
-        gemm_f64(d, 1.0, H, c.Bvv, 1.0, BV + (size_t)i0 * v, s, c.ws);
-      }
-      // BV[q][i][a] -= sum_(kk,P) Boo[P][i][kk] H[(kk,a)][(q,P)]   for kk in i0..i0+ib-1
-      {
-        GemmDesc d = gd(o, v, X, 0, (long)o * X, 1, kX, v);
-        d.KB = ib;
-        d.sAk = X;
-        d.sBk = (long)v * kX;
-        d.nb1 = k;
-        d.sB1 = X;
-        d.sC1 = N;
-        gemm_f64(d, -1.0, c.Boo_t + (size_t)i0 * X, H, 1.0, BV, s, c.ws);
-      }
-    };
-    double hflops = 0.0;
-    if (c.tau) {
-      // H[(i,c)][(q,P)] = sum_(j,d) tau[(i,c)][(j,d)] G[(q,P)][(j,d)]
-      GemmDesc d = gd((int)N, (int)kX, (int)N, 0, N, 1, N, kX);
+    // BV[q][i][a] -= sum_(kk,P) Boo[P][i][kk] H[(kk,a)][(q,P)]   kk in i0..i0+ib-1
+    {
+      GemmDesc d = gd(o, v, X, 0, (long)o * X, 1, kX, v);
+      d.KB = ib;
+      d.sAk = X;
+      d.sBk = (long)v * kX;
+      d.nb1 = k;
+      d.sB1 = X;
+      d.sC1 = N;
+      gemm_t<T>(d, mone, t.Boo_t + (size_t)i0 * X, H, one, BV, s, c.ws);
+    }
+  };
+  double hflops = 0.0;
+  if (t.tau) {
+    // H[(i,c)][(q,P)] = sum_(j,d) tau[(i,c)][(j,d)] G[(q,P)][(j,d)]
+    GemmDesc d = gd((int)N, (int)kX, (int)N, 0, N, 1, N, kX);
+    const int ev = c.events.start(s);
+    gemm_hhat_t<T>(d, one, t.tau, t.G, zero, t.H, s, c.ws);
+    c.events.stop(ev, s, 1);
+    hflops += gemm_flops(d);
+    c.stats.hhat_launches += 1;
+    outputs(t.H, 0, o);
+  } else {
+    const int ib = c.strip_rows;
+    for (int i0 = 0; i0 < o; i0 += ib) {
+      const int nb = std::min(ib, o - i0);
+      gemm_t<T>(gd(nb * v, (int)N, X, 1, N, 0, N, N), one, t.Bov + (size_t)i0 * v, t.Bov, zero, t.S, s, c.ws);
+      tau_strip_t(t.S, o, v, i0, nb, c.eps_o, c.eps_v, t.tau_w, s);
+      GemmDesc d = gd(nb * v, (int)kX, (int)N, 0, N, 1, N, kX);
       const int ev = c.events.start(s);
-      gemm_f64_hhat(d, 1.0, c.tau, G, 0.0, c.w_H, s, c.ws);
+      gemm_hhat_t<T>(d, one, t.tau_w, t.G, zero, t.H, s, c.ws);
       c.events.stop(ev, s, 1);
       hflops += gemm_flops(d);
       c.stats.hhat_launches += 1;
-      outputs(c.w_H, 0, o);
-    } else {
-      const int ib = c.strip_rows;
-      for (int i0 = 0; i0 < o; i0 += ib) {
-        const int nb = std::min(ib, o - i0);
-        gemm_f64(gd(nb * v, (int)N, X, 1, N, 0, N, N), 1.0, c.Bov + (size_t)i0 * v, c.Bov, 0.0, c.w_S, s, c.ws);
-        tau_strip(c.w_S, o, v, i0, nb, c.eps_o, c.eps_v, c.w_tau, nullptr, nullptr, nullptr, nullptr, s);
-        GemmDesc d = gd(nb * v, (int)kX, (int)N, 0, N, 1, N, kX);
-        const int ev = c.events.start(s);
-        gemm_f64_hhat(d, 1.0, c.w_tau, G, 0.0, c.w_H, s, c.ws);
-        c.events.stop(ev, s, 1);
-        hflops += gemm_flops(d);
-        c.stats.hhat_launches += 1;
-        outputs(c.w_H, i0, nb);
-      }
-    }
-    c.stats.hhat_flops += hflops;
-    // delta-type terms: P1 = V Gv, P2 = V Ev, P3 = Go V, P4 = Eo V
-    gemm_f64(gd(k * o, v, v, 0, v, 0, v, v), 1.0, V, c.Gv, 0.0, P1, s, c.ws);
-    gemm_f64(gd(k * o, v, v, 0, v, 0, v, v), 1.0, V, c.Ev, 0.0, P2, s, c.ws);
-    {
-      GemmDesc d = gd(o, v, o, 0, o, 0, v, v);
-      d.nb1 = k;
-      d.sB1 = N;
-      d.sC1 = N;
-      gemm_f64(d, 1.0, c.Go, V, 0.0, P3, s, c.ws);
-      gemm_f64(d, 1.0, c.Eo, V, 0.0, P4, s, c.ws);
+      outputs(t.H, i0, nb);
     }
   }
-  sigma_assemble(o, v, k, order, c.eps_o, c.eps_v, V, J, P1, P2, P3, P4, AV, BV, SV, s);
+  c.stats.hhat_flops += hflops;
+  // delta-type terms: P1 = V Gv, P2 = V Ev, P3 = Go V, P4 = Eo V
+  gemm_t<T>(gd(k * o, v, v, 0, v, 0, v, v), one, V, t.Gv, zero, P1, s, c.ws);
+  gemm_t<T>(gd(k * o, v, v, 0, v, 0, v, v), one, V, t.Ev, zero, P2, s, c.ws);
+  {
+    GemmDesc d = gd(o, v, o, 0, o, 0, v, v);
+    d.nb1 = k;
+    d.sB1 = N;
+    d.sC1 = N;
+    gemm_t<T>(d, one, t.Go, V, zero, P3, s, c.ws);
+    gemm_t<T>(d, one, t.Eo, V, zero, P4, s, c.ws);
+  }
+}
+
+}  // namespace
+
+void sigma_reserve(Context& c, int k, int precision) {
+  if (c.order < 1) return;
+  if (precision == 1)
+    grow_workspace32(c, k);
+  else
+    grow_workspace(c, k);
+}
+
+void sigma_core(Context& c, int order, int k, const double* V, double* AV, double* BV, double* SV) {
+  if (order > c.order) throw InvalidArg("requested order exceeds the setup order");
+  if (k <= 0) return;
+  hipStream_t s = c.stream;
+  const int o = c.o, v = c.v;
+  const long N = c.N;
+  if (order == 0) {
+    sigma_assemble(o, v, k, 0, c.eps_o, c.eps_v, V, nullptr, nullptr, nullptr, nullptr, nullptr, AV, BV, SV, s);
+    return;
+  }
+  grow_workspace(c, k);
+  if (c.events.pending() > 4096) c.resolve_stats();
+  const int ev_pass = c.events.start(s);
+  double* P1 = c.w_P;
+  double* P2 = P1 + (size_t)k * N;
+  double* P3 = P2 + (size_t)k * N;
+  double* P4 = P3 + (size_t)k * N;
+  contract<double>(c, ops64(c), order, k, V, AV, BV, c.w_J, P1, P2, P3, P4);
+  sigma_assemble(o, v, k, order, c.eps_o, c.eps_v, V, c.w_J, P1, P2, P3, P4, AV, BV, SV, s);
   c.events.stop(ev_pass, s, 0);
   c.stats.flops += sigma_flops(c, order, k);
   c.stats.vectors += k;
 }
 
-void sigma_core_f32(Context&, int, int, const double*, double*, double*, double*) {
-  throw NotSupported("FP32 product path not built");
+void sigma_core_f32(Context& c, int order, int k, const double* V, double* AV, double* BV, double* SV) {
+  if (order > c.order) throw InvalidArg("requested order exceeds the setup order");
+  if (k <= 0) return;
+  if (order >= 1 && !c.BovLam32) throw NotSupported("FP32 products need precision = PP_FP32 at setup");
+  hipStream_t s = c.stream;
+  const int o = c.o, v = c.v;
+  const long N = c.N;
+  if (order == 0) {
+    sigma_assemble(o, v, k, 0, c.eps_o, c.eps_v, V, nullptr, nullptr, nullptr, nullptr, nullptr, AV, BV, SV, s);
+    return;
+  }
+  grow_workspace32(c, k);
+  if (c.events.pending() > 4096) c.resolve_stats();
+  const int ev_pass = c.events.start(s);
+  const long kN = (long)k * N;
+  to_f32(kN, V, c.w32_V, s);
+  float* P1 = c.w32_P;
+  contract<float>(c, ops32(c), order, k, c.w32_V, c.w32_AV, c.w32_BV, c.w32_J, P1, P1 + kN, P1 + 2 * kN,
+                  P1 + 3 * kN);
+  // the diagonal (orbital-energy) term and the combination stay in FP64
+  to_f64(kN, c.w32_AV, AV, s);
+  to_f64(kN, c.w32_BV, BV, s);
+  to_f64(kN, c.w32_J, c.w_J, s);
+  if (order >= 2) to_f64(4 * kN, c.w32_P, c.w_P, s);
+  double* Q1 = c.w_P;
+  sigma_assemble(o, v, k, order, c.eps_o, c.eps_v, V, c.w_J, Q1, Q1 + kN, Q1 + 2 * kN, Q1 + 3 * kN, AV, BV, SV, s);
+  c.events.stop(ev_pass, s, 0);
+  c.stats.flops += sigma_flops(c, order, k);
+  c.stats.flops32 += sigma_flops(c, order, k);
+  c.stats.vectors += k;
 }
 
 }  // namespace ppw

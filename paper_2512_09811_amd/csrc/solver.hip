@@ -214,6 +214,43 @@ __global__ void residual_norms_kernel(long N, int nr, const double* __restrict__
   }
 }
 
+// Residuals of Ritz pairs from products of their halves: rows [u_0..u_nt-1, w_0..w_nt-1]
+// of V, AV, BV, SV.  out[j] = |ru|^2 + |rw|^2, out[nt + j] = |u|^2 + |w|^2 (= 2 |y|^2 and
+// |ru|^2 + |rw|^2 = 2 |r|^2, so |r|/|y| = sqrt(out[j] / out[nt + j])).
+__global__ void exact_residual_kernel(long N, int nt, const double* __restrict__ th, const double* __restrict__ V,
+                                      const double* __restrict__ AV, const double* __restrict__ BV,
+                                      const double* __restrict__ SV, double* __restrict__ out) {
+  __shared__ double red[2][kB / 64];
+  const int j = blockIdx.x;
+  const long bu = (long)j * N, bw = (long)(nt + j) * N;
+  const double t = th[j];
+  double a = 0.0, b = 0.0;
+  for (long i = threadIdx.x; i < N; i += blockDim.x) {
+    const double ru = AV[bu + i] + BV[bu + i] - t * SV[bw + i];
+    const double rw = AV[bw + i] - BV[bw + i] - t * SV[bu + i];
+    a += ru * ru + rw * rw;
+    b += V[bu + i] * V[bu + i] + V[bw + i] * V[bw + i];
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_down(a, off, 64);
+    b += __shfl_down(b, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = a;
+    red[1][threadIdx.x >> 6] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sa = 0, sb = 0;
+    for (int w = 0; w < kB / 64; ++w) {
+      sa += red[0][w];
+      sb += red[1][w];
+    }
+    out[j] = sa;
+    out[nt + j] = sb;
+  }
+}
+
 // corrections for the listed roots: solve [[ap, -th s], [-th s, am]] [cu; cw] = -[ru; rw]
 __global__ void correction_kernel(long N, int na, const int* __restrict__ idx_list, const double* __restrict__ th,
                                   double clampv, const double* __restrict__ dA, const double* __restrict__ dB,
@@ -368,6 +405,7 @@ class ProductBatcher {
   struct Req {
     int id = 0;
     int k = 0;
+    int prec = 0;  // 0: FP64 products, 1: FP32 contractions
     const double* V = nullptr;
     double *AV = nullptr, *BV = nullptr, *SV = nullptr;
     hipEvent_t ready = nullptr, done = nullptr;
@@ -386,7 +424,8 @@ class ProductBatcher {
     SV_ = c_.arena.alloc<double>(n, "batch SV");
     bufs_ = {V_, AV_, BV_, SV_};
     cap_ = ktot;
-    sigma_reserve(c_, ktot, prec_);
+    sigma_reserve(c_, ktot, 0);
+    if (prec_ == 1) sigma_reserve(c_, ktot, 1);
   }
   void multiply(Req& r) {
     std::unique_lock<std::mutex> lk(mu_);
@@ -409,29 +448,35 @@ class ProductBatcher {
     std::exception_ptr err;
     std::sort(pending_.begin(), pending_.end(), [](const Req* a, const Req* b) { return a->id < b->id; });
     try {
-      int kt = 0;
-      for (auto* r : pending_) kt += r->k;
-      if (kt > cap_) throw InvalidArg("product batch exceeds its reserved size");
       hipStream_t s = c_.stream;
       const long N = c_.N;
-      long off = 0;
-      for (auto* r : pending_) {
-        PPW_HIP(hipStreamWaitEvent(s, r->ready, 0));
-        PPW_HIP(hipMemcpyAsync(V_ + off * N, r->V, sizeof(double) * r->k * N, hipMemcpyDeviceToDevice, s));
-        off += r->k;
-      }
-      if (prec_ == 1)
-        sigma_core_f32(c_, c_.order, kt, V_, AV_, BV_, SV_);
-      else
-        sigma_core(c_, c_.order, kt, V_, AV_, BV_, SV_);
-      off = 0;
-      for (auto* r : pending_) {
-        const size_t b = sizeof(double) * r->k * N;
-        PPW_HIP(hipMemcpyAsync(r->AV, AV_ + off * N, b, hipMemcpyDeviceToDevice, s));
-        PPW_HIP(hipMemcpyAsync(r->BV, BV_ + off * N, b, hipMemcpyDeviceToDevice, s));
-        PPW_HIP(hipMemcpyAsync(r->SV, SV_ + off * N, b, hipMemcpyDeviceToDevice, s));
-        PPW_HIP(hipEventRecord(r->done, s));
-        off += r->k;
+      for (int prec = 0; prec < 2; ++prec) {
+        int kt = 0;
+        for (auto* r : pending_)
+          if (r->prec == prec) kt += r->k;
+        if (kt == 0) continue;
+        if (kt > cap_) throw InvalidArg("product batch exceeds its reserved size");
+        long off = 0;
+        for (auto* r : pending_) {
+          if (r->prec != prec) continue;
+          PPW_HIP(hipStreamWaitEvent(s, r->ready, 0));
+          PPW_HIP(hipMemcpyAsync(V_ + off * N, r->V, sizeof(double) * r->k * N, hipMemcpyDeviceToDevice, s));
+          off += r->k;
+        }
+        if (prec == 1)
+          sigma_core_f32(c_, c_.order, kt, V_, AV_, BV_, SV_);
+        else
+          sigma_core(c_, c_.order, kt, V_, AV_, BV_, SV_);
+        off = 0;
+        for (auto* r : pending_) {
+          if (r->prec != prec) continue;
+          const size_t b = sizeof(double) * r->k * N;
+          PPW_HIP(hipMemcpyAsync(r->AV, AV_ + off * N, b, hipMemcpyDeviceToDevice, s));
+          PPW_HIP(hipMemcpyAsync(r->BV, BV_ + off * N, b, hipMemcpyDeviceToDevice, s));
+          PPW_HIP(hipMemcpyAsync(r->SV, SV_ + off * N, b, hipMemcpyDeviceToDevice, s));
+          PPW_HIP(hipEventRecord(r->done, s));
+          off += r->k;
+        }
       }
     } catch (...) {
       err = std::current_exception();
@@ -625,10 +670,11 @@ class Solver {
 
   // A, B, S products of k orthonormal vectors X (device, [k][N]) into AV_, BV_, SV_,
   // merged with the other windows' requests by the batcher
-  void products(int k, const double* X) {
+  void products(int k, const double* X, bool exact) {
     ProductBatcher::Req r;
     r.id = id_;
     r.k = k;
+    r.prec = (exact || opt_.precision != 1) ? 0 : 1;
     r.V = X;
     r.AV = AV_;
     r.BV = BV_;
@@ -704,7 +750,7 @@ class Solver {
     scale_cols_kernel<<<gridn((long)(nb0 + n2) * kk), kB, 0, s_>>>(Ctot_, nb0 + n2, kk, kk, nrm_, 0);
     // products of the new orthonormal vectors
     if (n2 > 0) {
-      products(n2, Q_ + (size_t)nb0 * N_);
+      products(n2, Q_ + (size_t)nb0 * N_, false);
       axpby((long)n2 * N_, 1.0, AV_, 0.0, P0_ + (size_t)nb0 * N_, s_);
       axpby((long)n2 * N_, 1.0, BV_, 1.0, P0_ + (size_t)nb0 * N_, s_);
       axpby((long)n2 * N_, 1.0, AV_, 0.0, P1_ + (size_t)nb0 * N_, s_);
@@ -766,14 +812,45 @@ class Solver {
     // Kc = tmp T  (n x nk)
     small_mm(n, nk, kk, tmp_, kk, 0, Tm_, nk, 0, tmp2_, nk);
     expand(nk, n, tmp2_, nk, Q_, Qs_);
-    expand(nk, n, tmp2_, nk, P0_, P0s_);
-    expand(nk, n, tmp2_, nk, P1_, P1s_);
-    expand(nk, n, tmp2_, nk, PS_, PSs_);
+    if (opt_.precision == 1) {
+      // mixed precision: the restart block gets FP64 products (refinement)
+      products(nk, Qs_, true);
+      axpby((long)nk * N_, 1.0, AV_, 0.0, P0s_, s_);
+      axpby((long)nk * N_, 1.0, BV_, 1.0, P0s_, s_);
+      axpby((long)nk * N_, 1.0, AV_, 0.0, P1s_, s_);
+      axpby((long)nk * N_, -1.0, BV_, 1.0, P1s_, s_);
+      PPW_HIP(hipMemcpyAsync(PSs_, SV_, sizeof(double) * nk * N_, hipMemcpyDeviceToDevice, s_));
+    } else {
+      expand(nk, n, tmp2_, nk, P0_, P0s_);
+      expand(nk, n, tmp2_, nk, P1_, P1s_);
+      expand(nk, n, tmp2_, nk, PS_, PSs_);
+    }
     std::swap(Q_, Qs_);
     std::swap(P0_, P0s_);
     std::swap(P1_, P1s_);
     std::swap(PS_, PSs_);
     nb_ = nk;
+  }
+
+  // FP64 residual norms |(M - theta Sigma) y| / |y| of the listed Ritz pairs, from
+  // FP64 products of their X+Y and X-Y halves.
+  std::vector<double> exact_residuals(const std::vector<int>& tg, const std::vector<double>& th) {
+    const int nt = (int)tg.size();
+    const int n = nb_;
+    upload(sel_, tg);
+    gather_cols_kernel<<<gridn((long)n * nt), kB, 0, s_>>>(n, nt, sel_, us_, rld_, c1_, nt, 0);
+    gather_cols_kernel<<<gridn((long)n * nt), kB, 0, s_>>>(n, nt, sel_, ws_, rld_, c2_, nt, 0);
+    expand(nt, n, c1_, nt, Q_, V_);
+    expand(nt, n, c2_, nt, Q_, V_ + (size_t)nt * N_);
+    products(2 * nt, V_, true);
+    std::vector<double> ths(nt);
+    for (int q = 0; q < nt; ++q) ths[q] = th[tg[q]];
+    upload(th2_, ths);
+    exact_residual_kernel<<<nt, kB, 0, s_>>>(N_, nt, th2_, V_, AV_, BV_, SV_, stats_);
+    auto st = fetch(stats_, 2 * (size_t)nt);
+    std::vector<double> out(nt);
+    for (int q = 0; q < nt; ++q) out[q] = std::sqrt(st[q] / st[nt + q]);
+    return out;
   }
 
   struct Ritz {
@@ -885,7 +962,13 @@ void Solver::run(double* energies, double* vectors, double* osc, pp_solve_info* 
   bool converged = false;
   int cycle = 0;
   const double clampv = opt_.d_clamp > 0 ? opt_.d_clamp : 1e-4;
+  const bool mixed = opt_.precision == 1;
+  bool refined = !mixed;  // mixed precision: becomes true after the first FP64 restart
+  const double switch_tol = std::max(opt_.tol, 1e-7);
+  double best_worst = 1e300;
+  int since_best = 0;
   for (cycle = 0; cycle < opt_.max_cycles; ++cycle) {
+   if (knew > 0) {
     // X, Y halves are contiguous in V_: [X_0..X_k-1, Y_0..Y_k-1]
     const int kk = 2 * knew;
     extend(V_, kk);
@@ -945,6 +1028,7 @@ void Solver::run(double* energies, double* vectors, double* osc, pp_solve_info* 
       axpy_cols_kernel<<<gridn((long)nb_ * knew), kB, 0, s_>>>(nb_, knew, kmax_, alpha_, cdx_, kmax_, cx_);
       axpy_cols_kernel<<<gridn((long)nb_ * knew), kB, 0, s_>>>(nb_, knew, kmax_, alpha_, cdy_, kmax_, cy_);
     }
+   }
     R = rayleigh_ritz();
     const int n = (int)R.th.size();
     std::vector<int> order(n);
@@ -953,8 +1037,55 @@ void Solver::run(double* energies, double* vectors, double* osc, pp_solve_info* 
     blk.assign(order.begin(), order.begin() + std::min(m_, n));
     tgt.assign(order.begin(), order.begin() + std::min(nr_, n));
     bool all = (int)tgt.size() == nr_;
-    for (int j : tgt) all = all && R.rn[j] <= opt_.tol;
-    if (all) {
+    double worst = 0.0;
+    for (int j : tgt) {
+      all = all && R.rn[j] <= opt_.tol;
+      worst = std::max(worst, R.rn[j]);
+    }
+    if (worst < 0.5 * best_worst) {
+      best_worst = worst;
+      since_best = 0;
+    } else {
+      ++since_best;
+    }
+    const bool stalled = since_best >= 5;
+    if (mixed) {
+      // FP32 products build the subspace; restart blocks get FP64 products; the
+      // returned vectors are accepted on FP64 residuals only.
+      if (!refined && (all || worst <= switch_tol || stalled)) {
+        restart(blk);
+        refined = true;
+        knew = 0;
+        best_worst = 1e300;
+        since_best = 0;
+        continue;
+      }
+      if (refined && all) {
+        auto rex = exact_residuals(tgt, R.th);
+        bool ok = true;
+        for (size_t q = 0; q < tgt.size(); ++q) {
+          R.rn[tgt[q]] = rex[q];
+          ok = ok && rex[q] <= opt_.tol;
+        }
+        if (ok) {
+          converged = true;
+          ++cycle;
+          break;
+        }
+        restart(blk);
+        knew = 0;
+        best_worst = 1e300;
+        since_best = 0;
+        continue;
+      }
+      if (refined && stalled) {
+        restart(blk);
+        knew = 0;
+        best_worst = 1e300;
+        since_best = 0;
+        continue;
+      }
+    } else if (all) {
       converged = true;
       ++cycle;
       break;

@@ -148,3 +148,34 @@ def test_window_batch_matches_single_and_oracle(P):
     with P.Handle.from_system(sys, order=2) as h:
         eb2, _, fb2, _ = h.window_solve_batch(omegas, 6)
     assert np.array_equal(eb, eb2) and np.array_equal(fb, fb2)
+
+
+def test_fp32_products_within_single_precision(P):
+    """FP32 contractions + FP64 diagonal/assembly: products agree with the oracle to FP32 accuracy."""
+    torch = pytest.importorskip("torch")
+    sys = _sys("mid")
+    X = random_block(5, sys.N, 2)
+    V = torch.tensor(np.concatenate([X[:, 0], X[:, 1]]), dtype=torch.float64, device="cuda")
+    k = V.shape[0]
+    outs = [torch.empty_like(V) for _ in range(6)]
+    A, B, S = dense.assemble(sys, 2)
+    with P.Handle.from_system(sys, order=2, precision=P.PP_FP32) as h:
+        h.products(V, outs[0], outs[1], outs[2], fp32=False)
+        h.products(V, outs[3], outs[4], outs[5], fp32=True)
+    Vh = V.cpu().numpy()
+    ref = [(A @ Vh.T).T, (B @ Vh.T).T, (S @ Vh.T).T]
+    for j in range(3):
+        np.testing.assert_allclose(outs[j].cpu().numpy(), ref[j], rtol=0, atol=1e-12 * np.abs(ref[j]).max())
+        corr = ref[j] - (Vh * np.diag(A if j == 0 else (B if j == 1 else S))) if j < 2 else ref[j] - Vh
+        err = np.abs(outs[3 + j].cpu().numpy() - ref[j]).max()
+        assert err <= 2e-6 * np.abs(corr).max() + 1e-14, (j, err, np.abs(corr).max())
+
+
+@pytest.mark.parametrize("omega0,nr", [(0.45, 8), (1.1, 8)])
+def test_window_mixed_precision(P, omega0, nr):
+    """FP32 subspace products with FP64 restarts and FP64 residual acceptance meet the FP64 bar."""
+    sys = gen(7, 12, 40, 100)
+    with P.Handle.from_system(sys, order=2, precision=P.PP_FP32) as h:
+        e, vec, f, info = h.window_solve(omega0, nr)
+    _check_window(sys, 2, omega0, nr, e, vec, f, info)
+    assert np.all(info["residual"] <= 1e-9)
