@@ -201,7 +201,12 @@ __global__ __launch_bounds__(kT) void syev_kernel(int n, const double* __restric
       }
       __syncthreads();
       const int mm = ctl[0], nrot = ctl[1];
-      if (mm == l || ctl[2]) break;
+      const bool done = mm == l || ctl[2];
+      // every thread holds its copy of ctl before thread 0 may rewrite it (for the
+      // next sweep or the next l); without this barrier a late wave can read the
+      // next values, miss the break and spin on a ctl that no thread updates
+      __syncthreads();
+      if (done) break;
       // apply rotations i = mm-1, mm-2, ... to columns (i, i+1) of Z, one row per thread
       for (int row = tid; row < n; row += kT) {
         for (int t = 0; t < nrot; ++t) {

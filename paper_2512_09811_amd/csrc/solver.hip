@@ -25,6 +25,8 @@
 // folded quotient) and eigenvalue lists that decide which directions to keep.
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <condition_variable>
 #include <exception>
 #include <memory>
@@ -508,6 +510,7 @@ class Solver {
     nbmax_ = (int)std::min<long>(o.max_basis > 0 ? o.max_basis : 400, N_);
     nbmax_ = std::max(nbmax_, std::min<int>((int)N_, 2 * m_));
     kmax_ = 2 * m_;  // new vectors per extension (X and Y halves of a block)
+    trace_ = std::getenv("PPWIN_TRACE") != nullptr;
     PPW_HIP(hipStreamCreateWithFlags(&s_, hipStreamNonBlocking));
     PPW_HIP(hipEventCreateWithFlags(&ev_ready_, hipEventDisableTiming));
     PPW_HIP(hipEventCreateWithFlags(&ev_done_, hipEventDisableTiming));
@@ -534,6 +537,8 @@ class Solver {
   ProductBatcher* pb_;
   int id_;
   hipEvent_t ev_ready_ = nullptr, ev_done_ = nullptr;
+  bool trace_ = false;  // per-cycle progress on stderr when PPWIN_TRACE is set
+  bool refined_ = false;  // mixed precision: every product FP64 from here on
   Workspace wsp_;
   int nb_ = 0;
   int rld_ = 1;  // columns (leading dimension) of the current Ritz coefficient matrices us_/ws_
@@ -674,7 +679,7 @@ class Solver {
     ProductBatcher::Req r;
     r.id = id_;
     r.k = k;
-    r.prec = (exact || opt_.precision != 1) ? 0 : 1;
+    r.prec = (exact || opt_.precision != 1 || refined_) ? 0 : 1;
     r.V = X;
     r.AV = AV_;
     r.BV = BV_;
@@ -1049,10 +1054,14 @@ void Solver::run(double* energies, double* vectors, double* osc, pp_solve_info* 
       ++since_best;
     }
     const bool stalled = since_best >= 5;
+    if (trace_)
+      std::fprintf(stderr, "[ppwin] window %d omega0 %.4f cycle %d basis %d products %ld worst %.3e refined %d\n", id_,
+                   w0_, cycle, nb_, products_, worst, refined ? 1 : 0);
     if (mixed) {
       // FP32 products build the subspace; restart blocks get FP64 products; the
       // returned vectors are accepted on FP64 residuals only.
       if (!refined && (all || worst <= switch_tol || stalled)) {
+        refined_ = true;
         restart(blk);
         refined = true;
         knew = 0;
@@ -1062,6 +1071,11 @@ void Solver::run(double* energies, double* vectors, double* osc, pp_solve_info* 
       }
       if (refined && all) {
         auto rex = exact_residuals(tgt, R.th);
+        if (trace_) {
+          double mx = 0.0;
+          for (double x : rex) mx = std::max(mx, x);
+          std::fprintf(stderr, "[ppwin] window %d FP64 residual check: worst %.3e\n", id_, mx);
+        }
         bool ok = true;
         for (size_t q = 0; q < tgt.size(); ++q) {
           R.rn[tgt[q]] = rex[q];
