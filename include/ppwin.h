@@ -50,7 +50,8 @@ typedef enum {
   PP_ENOTCONV = 3,   /* solve stopped at max_cycles; outputs written, info->converged flags 0 */
   PP_EUNSTABLE = 4,  /* A-B, A+B or S not positive definite in the subspace (complex roots) */
   PP_EDEVICE = 5,    /* HIP runtime error; message kept */
-  PP_ENOTSUP = 6     /* option combination not supported */
+  PP_ENOTSUP = 6,    /* option combination not supported */
+  PP_EPENDING = 7    /* server request not finished yet (pp_server_poll) */
 } pp_status;
 
 typedef enum {
@@ -172,6 +173,91 @@ uint64_t pp_device_bytes(const pp_handle* h);
 
 /* Frees every device allocation of the handle.  NULL is accepted. */
 pp_status pp_destroy(pp_handle* h);
+
+/* ------------------------------------------------------------------------
+ * Serving: a persistent request loop for window solves of differing systems.
+ *
+ * Not in the paper (which solves one system at a time); it serves many
+ * (system, omega0, n_roots) requests on one GPU with continuous batching:
+ *  - pp_server_submit copies the request's inputs to host memory owned by the
+ *    server and returns at once; requests are admitted in arrival order as soon
+ *    as their device footprint (inputs, second-order intermediates, amplitudes
+ *    when stored, product workspaces, subspace) fits the server's HBM budget
+ *    and a solve slot is free;
+ *  - each admitted request is set up on its own stream while earlier requests
+ *    keep solving; its B tensors and subspace stay resident until it retires;
+ *  - the products of all requests that are solving are merged into shared
+ *    passes: each contraction step of the product is issued for every request at
+ *    once, its GEMMs (different shapes) merged into grouped matrix-core launches;
+ *  - a request retires when its window has converged (or failed); its device
+ *    memory is released and the next queued requests are admitted.
+ * Each request's result equals that of pp_window_solve on its own handle with the
+ * same options, within the solver tolerance.  The server object is thread-safe.
+ * ------------------------------------------------------------------------ */
+typedef struct pp_server pp_server;
+
+/* Result of one request.  The caller sets the output pointers (each nullable,
+ * host memory of the sizes given) before pp_server_poll / pp_server_wait; the
+ * remaining fields are written by the server. */
+typedef struct {
+  double* energies;        /* [n_roots] ascending (Ha) */
+  double* vectors;         /* [n_roots][2][n_occ][n_vir], X^T S X - Y^T S Y = 1 */
+  double* osc;             /* [n_roots] oscillator strengths (0 when the system had no dip) */
+  int32_t n_roots;         /* roots written */
+  int32_t status;          /* pp_status of the solve (PP_OK, PP_ENOTCONV, PP_ENOMEM, ...) */
+  pp_solve_info info;
+  double queued_seconds;   /* submit -> admission */
+  double run_seconds;      /* admission -> retirement (setup + solve) */
+  double latency_seconds;  /* submit -> retirement */
+} pp_result;
+
+typedef struct {
+  int64_t submitted, completed, failed, queued, running;
+  int32_t peak_running;
+  double latency_p50, latency_p99;   /* submit -> retirement over completed requests (s) */
+  double queued_p50, queued_p99;     /* submit -> admission (s) */
+  double solves_per_second;          /* completed / (last retirement - first submission) */
+  int64_t passes;                    /* merged product passes */
+  double mean_requests_per_pass;
+  double product_flops;              /* algorithmic flops of all passes */
+  double product_seconds;            /* device time of all passes (events on the pass stream) */
+  uint64_t budget_bytes, reserved_bytes, peak_reserved_bytes;
+  int64_t grouped_launches;          /* GEMM launches that served several requests at once */
+} pp_server_stats;
+
+/* opt: options applied to every request (NULL: defaults; hbm_budget, stream and
+ * store_amplitudes are chosen per request by the server).  hbm_budget: device
+ * bytes all admitted requests may hold together (0: 85% of free device memory).
+ * max_active: requests solving at once (0: 8; at most 8). */
+pp_status pp_server_create(const pp_options* opt, uint64_t hbm_budget, int32_t max_active, pp_server** out);
+
+/* Queues a window solve of 'sys' (order 1 or 2; host arrays, copied before the
+ * call returns).  PP_ENOMEM when its footprint alone exceeds the budget (nothing
+ * queued), PP_EINVAL for bad sizes, non-finite inputs or device pointers. */
+pp_status pp_server_submit(pp_server* srv, const pp_system* sys, double omega0, int32_t n_roots, uint64_t* req_id);
+
+/* Device bytes the server would reserve for this request (its admission
+ * footprint: an upper bound of what its setup, product workspace and subspace
+ * allocate); 0 for invalid arguments.  Only the sizes and order of sys are read. */
+uint64_t pp_server_request_bytes(const pp_server* srv, const pp_system* sys, int32_t n_roots);
+
+/* Delivers a finished request's result into *res and forgets the request
+ * (a second poll/wait of the same id returns PP_EINVAL).  Returns PP_EPENDING
+ * (nothing written) while it is queued or running, otherwise the request's own
+ * status (also in res->status). */
+pp_status pp_server_poll(pp_server* srv, uint64_t req_id, pp_result* res);
+/* As pp_server_poll, blocking until the request has finished. */
+pp_status pp_server_wait(pp_server* srv, uint64_t req_id, pp_result* res);
+
+/* Counters and latency percentiles since creation (or the last reset). */
+pp_status pp_server_stats_get(pp_server* srv, pp_server_stats* st);
+pp_status pp_server_stats_reset(pp_server* srv);
+
+/* Finishes the running requests, drops the queued ones and frees everything. */
+pp_status pp_server_destroy(pp_server* srv);
+
+/* Last error message of the server (submit-time errors). */
+const char* pp_server_last_error(const pp_server* srv);
 
 const char* pp_status_string(pp_status s);
 /* Last error message of the handle (NULL handle: last error of pp_setup in this thread). */

@@ -26,6 +26,22 @@ pp_status ppint_gemm(int32_t fp32, int32_t M, int32_t N, int32_t K, int32_t KB, 
                      int64_t ldc, int64_t sC, double alpha, const void* A, const void* B, double beta, void* C,
                      uint64_t ws_bytes);
 
+/* One member of ppint_gemm_group (layouts as in ppint_gemm, no batch). */
+typedef struct {
+  int32_t M, N, K, transA, transB;
+  int64_t lda, ldb, ldc;
+  const void* A;
+  const void* B;
+  void* C;
+  double alpha, beta;
+} ppint_gemm_member;
+
+/* n independent GEMMs issued together: members sharing a tile shape are merged
+ * into grouped launches when together they fill the chip (the path the serving
+ * loop's merged product passes take); returns, in *grouped_launches (nullable),
+ * how many grouped launches were made. */
+pp_status ppint_gemm_group(int32_t fp32, int32_t n, const ppint_gemm_member* members, int32_t* grouped_launches);
+
 /* Symmetric eigen-decomposition of an n x n row-major matrix A (device, lda = n)
  * by the library's one-workgroup FP64 solver: w ascending, Z columns = vectors
  * (row-major n x n, Z[r*n + c] = component r of vector c). */

@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libppwin.so")
 
-PP_OK, PP_EINVAL, PP_ENOMEM, PP_ENOTCONV, PP_EUNSTABLE, PP_EDEVICE, PP_ENOTSUP = range(7)
+PP_OK, PP_EINVAL, PP_ENOMEM, PP_ENOTCONV, PP_EUNSTABLE, PP_EDEVICE, PP_ENOTSUP, PP_EPENDING = range(8)
 PP_FP64, PP_FP32 = 0, 1
 PP_APPLY_METRIC = 1
 PP_DEVICE_PTRS = 2
@@ -52,6 +52,27 @@ class pp_solve_info(C.Structure):
 class pp_stats(C.Structure):
     _fields_ = [("product_flops", C.c_double), ("product_seconds", C.c_double), ("product_vectors", C.c_int64),
                 ("hhat_flops", C.c_double), ("hhat_seconds", C.c_double), ("hhat_launches", C.c_int64)]
+
+
+class ppint_gemm_member(C.Structure):
+    _fields_ = [("M", C.c_int32), ("N", C.c_int32), ("K", C.c_int32), ("transA", C.c_int32), ("transB", C.c_int32),
+                ("lda", C.c_int64), ("ldb", C.c_int64), ("ldc", C.c_int64), ("A", C.c_void_p), ("B", C.c_void_p),
+                ("C", C.c_void_p), ("alpha", C.c_double), ("beta", C.c_double)]
+
+
+class pp_result(C.Structure):
+    _fields_ = [("energies", C.c_void_p), ("vectors", C.c_void_p), ("osc", C.c_void_p), ("n_roots", C.c_int32),
+                ("status", C.c_int32), ("info", pp_solve_info), ("queued_seconds", C.c_double),
+                ("run_seconds", C.c_double), ("latency_seconds", C.c_double)]
+
+
+class pp_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64), ("queued", C.c_int64),
+                ("running", C.c_int64), ("peak_running", C.c_int32), ("latency_p50", C.c_double),
+                ("latency_p99", C.c_double), ("queued_p50", C.c_double), ("queued_p99", C.c_double),
+                ("solves_per_second", C.c_double), ("passes", C.c_int64), ("mean_requests_per_pass", C.c_double),
+                ("product_flops", C.c_double), ("product_seconds", C.c_double), ("budget_bytes", C.c_uint64),
+                ("reserved_bytes", C.c_uint64), ("peak_reserved_bytes", C.c_uint64), ("grouped_launches", C.c_int64)]
 
 
 _lib = None
@@ -101,12 +122,32 @@ def lib() -> C.CDLL:
         L.ppint_gemm.argtypes = [i32, i32, i32, i32, i32, i32, i32, i64, i64, i64, i32, i64, i64, i64, i64, i64,
                                  dbl, vp, vp, dbl, vp, u64]
         L.ppint_gemm.restype = C.c_int
+        L.ppint_gemm_group.argtypes = [i32, i32, C.POINTER(ppint_gemm_member), C.POINTER(i32)]
+        L.ppint_gemm_group.restype = C.c_int
         L.ppint_syev.argtypes = [i32, vp, vp, vp]
         L.ppint_syev.restype = C.c_int
         L.ppint_cholesky.argtypes = [i32, vp, vp]
         L.ppint_cholesky.restype = C.c_int
         L.ppint_products.argtypes = [vp, i32, i32, vp, vp, vp, vp, i32]
         L.ppint_products.restype = C.c_int
+        L.pp_server_create.argtypes = [C.POINTER(pp_options), u64, i32, C.POINTER(vp)]
+        L.pp_server_create.restype = C.c_int
+        L.pp_server_submit.argtypes = [vp, C.POINTER(pp_system), dbl, i32, C.POINTER(u64)]
+        L.pp_server_submit.restype = C.c_int
+        L.pp_server_request_bytes.argtypes = [vp, C.POINTER(pp_system), i32]
+        L.pp_server_request_bytes.restype = u64
+        L.pp_server_poll.argtypes = [vp, u64, C.POINTER(pp_result)]
+        L.pp_server_poll.restype = C.c_int
+        L.pp_server_wait.argtypes = [vp, u64, C.POINTER(pp_result)]
+        L.pp_server_wait.restype = C.c_int
+        L.pp_server_stats_get.argtypes = [vp, C.POINTER(pp_server_stats)]
+        L.pp_server_stats_get.restype = C.c_int
+        L.pp_server_stats_reset.argtypes = [vp]
+        L.pp_server_stats_reset.restype = C.c_int
+        L.pp_server_destroy.argtypes = [vp]
+        L.pp_server_destroy.restype = C.c_int
+        L.pp_server_last_error.argtypes = [vp]
+        L.pp_server_last_error.restype = C.c_char_p
         _lib = L
     return _lib
 
@@ -274,9 +315,114 @@ def gemm(A, B, C_, *, M, N, K, KB=1, nbatch=1, transA=0, lda, sA=0, sAk=0, trans
     _check(st)
 
 
+def gemm_group(members, fp32=False) -> int:
+    """Grouped GEMM test hook: members are dicts with torch device tensors A, B, C and
+    M, N, K, transA, transB, lda, ldb, ldc, alpha, beta.  Returns the grouped launch count."""
+    arr = (ppint_gemm_member * len(members))()
+    for i, m in enumerate(members):
+        arr[i] = ppint_gemm_member(M=m["M"], N=m["N"], K=m["K"], transA=m["transA"], transB=m["transB"],
+                                   lda=m["lda"], ldb=m["ldb"], ldc=m["ldc"], A=m["A"].data_ptr(),
+                                   B=m["B"].data_ptr(), C=m["C"].data_ptr(), alpha=m.get("alpha", 1.0),
+                                   beta=m.get("beta", 0.0))
+    g = C.c_int32()
+    _check(lib().ppint_gemm_group(1 if fp32 else 0, len(members), arr, C.byref(g)))
+    return g.value
+
+
 def syev(A, w, Z):
     _check(lib().ppint_syev(A.shape[0], A.data_ptr(), w.data_ptr(), Z.data_ptr()))
 
 
 def cholesky(A, L_):
     _check(lib().ppint_cholesky(A.shape[0], A.data_ptr(), L_.data_ptr()))
+
+
+class Server:
+    """The serving loop (wraps pp_server*): submit window solves of differing systems,
+    collect results; requests solving together share merged product passes."""
+
+    def __init__(self, hbm_budget: int = 0, max_active: int = 0, **opts):
+        L = lib()
+        o = default_options(**opts)
+        h = C.c_void_p()
+        st = L.pp_server_create(C.byref(o), hbm_budget, max_active, C.byref(h))
+        if st != PP_OK:
+            raise PPError(st, f"{L.pp_status_string(st).decode()}: {L.pp_server_last_error(None).decode()}")
+        self.h = h
+        self._meta = {}
+
+    def _check(self, st):
+        if st != PP_OK:
+            L = lib()
+            raise PPError(st, f"{L.pp_status_string(st).decode()}: {L.pp_server_last_error(self.h).decode()}")
+
+    def submit(self, eps, B_oo, B_ov, B_vv, dip, omega0: float, n_roots: int, order: int = 2) -> int:
+        arrs = [_f64(eps), _f64(B_oo), _f64(B_ov), _f64(B_vv)] + ([_f64(dip)] if dip is not None else [])
+        naux, o, v = arrs[2].shape
+        s = pp_system(n_occ=o, n_vir=v, n_aux=naux, order=order, eps=arrs[0].ctypes.data,
+                      B_oo=arrs[1].ctypes.data, B_ov=arrs[2].ctypes.data, B_vv=arrs[3].ctypes.data,
+                      dip=arrs[4].ctypes.data if dip is not None else None, device_ptrs=0)
+        rid = C.c_uint64()
+        self._check(lib().pp_server_submit(self.h, C.byref(s), float(omega0), int(n_roots), C.byref(rid)))
+        self._meta[rid.value] = (o * v, int(n_roots))
+        return rid.value
+
+    def request_bytes(self, o: int, v: int, naux: int, n_roots: int, order: int = 2, dip: bool = True) -> int:
+        dummy = np.zeros(1)
+        s = pp_system(n_occ=o, n_vir=v, n_aux=naux, order=order, eps=dummy.ctypes.data, B_oo=dummy.ctypes.data,
+                      B_ov=dummy.ctypes.data, B_vv=dummy.ctypes.data, dip=dummy.ctypes.data if dip else None,
+                      device_ptrs=0)
+        return int(lib().pp_server_request_bytes(self.h, C.byref(s), int(n_roots)))
+
+    def submit_system(self, sys, omega0: float, n_roots: int, order: int = 2) -> int:
+        return self.submit(sys.eps, sys.B_oo, sys.B_ov, sys.B_vv, sys.dip, omega0, n_roots, order)
+
+    def _take(self, rid: int, block: bool, allow_unconverged: bool):
+        N, nr = self._meta[rid]
+        e = np.zeros(nr)
+        vec = np.zeros((nr, 2, N))
+        f = np.zeros(nr)
+        res = pp_result(energies=e.ctypes.data, vectors=vec.ctypes.data, osc=f.ctypes.data)
+        fn = lib().pp_server_wait if block else lib().pp_server_poll
+        st = fn(self.h, rid, C.byref(res))
+        if st == PP_EPENDING:
+            return None
+        del self._meta[rid]
+        if not (st == PP_OK or (st == PP_ENOTCONV and allow_unconverged)):
+            self._check(st)
+        info = res.info
+        return dict(energies=e, vectors=vec, osc=f, status=st, n_roots=res.n_roots,
+                    queued_seconds=res.queued_seconds, run_seconds=res.run_seconds,
+                    latency_seconds=res.latency_seconds, products=info.products, cycles=info.cycles,
+                    residual=np.array(info.residual[:nr]), converged=np.array(info.converged[:nr]))
+
+    def wait(self, rid: int, allow_unconverged: bool = False):
+        return self._take(rid, True, allow_unconverged)
+
+    def poll(self, rid: int, allow_unconverged: bool = False):
+        return self._take(rid, False, allow_unconverged)
+
+    def stats(self) -> dict:
+        st = pp_server_stats()
+        self._check(lib().pp_server_stats_get(self.h, C.byref(st)))
+        return {name: getattr(st, name) for name, _ in pp_server_stats._fields_}
+
+    def reset_stats(self):
+        self._check(lib().pp_server_stats_reset(self.h))
+
+    def close(self):
+        if self.h:
+            lib().pp_server_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -10,6 +10,7 @@
 #include "context.h"
 #include "kernels.h"
 #include "solver.h"
+#include "abi.h"
 
 struct pp_handle {
   ppw::Context* ctx = nullptr;
@@ -20,43 +21,7 @@ struct pp_handle {
 namespace {
 
 thread_local std::string g_setup_error;
-
-template <typename F>
-pp_status guarded(std::string* err, F&& f) {
-  try {
-    f();
-    return PP_OK;
-  } catch (const ppw::InvalidArg& e) {
-    if (err) *err = e.what();
-    return PP_EINVAL;
-  } catch (const ppw::OutOfBudget& e) {
-    if (err) *err = e.what();
-    return PP_ENOMEM;
-  } catch (const ppw::NotConverged& e) {
-    if (err) *err = e.what();
-    return PP_ENOTCONV;
-  } catch (const ppw::Unstable& e) {
-    if (err) *err = e.what();
-    return PP_EUNSTABLE;
-  } catch (const ppw::NotSupported& e) {
-    if (err) *err = e.what();
-    return PP_ENOTSUP;
-  } catch (const ppw::DeviceError& e) {
-    if (err) *err = e.what();
-    return PP_EDEVICE;
-  } catch (const std::exception& e) {
-    if (err) *err = e.what();
-    return PP_EDEVICE;
-  } catch (...) {
-    if (err) *err = "unknown error";
-    return PP_EDEVICE;
-  }
-}
-
-void check_finite(const double* p, size_t n, const char* what) {
-  for (size_t i = 0; i < n; ++i)
-    if (!std::isfinite(p[i])) throw ppw::InvalidArg(std::string("non-finite value in ") + what);
-}
+using ppw::guarded;
 
 }  // namespace
 
@@ -89,23 +54,11 @@ pp_status pp_setup(const pp_system* sys, const pp_options* opt_in, pp_handle** o
     pp_options opt;
     pp_default_options(&opt);
     if (opt_in) opt = *opt_in;
-    if (opt.precision != PP_FP64 && opt.precision != PP_FP32) throw ppw::InvalidArg("unknown precision");
-    if (opt.max_basis > 512) throw ppw::InvalidArg("max_basis must be <= 512");
-    if (!(opt.tol > 0)) throw ppw::InvalidArg("tol must be positive");
+    ppw::check_options(opt);
     const int o = sys->n_occ, v = sys->n_vir, X = sys->n_aux;
     if (o < 1 || v < 1 || X < 1) throw ppw::InvalidArg("n_occ, n_vir and n_aux must be positive");
     if (!sys->eps || !sys->B_oo || !sys->B_ov || !sys->B_vv) throw ppw::InvalidArg("NULL input array");
-    if (!sys->device_ptrs) {
-      const size_t N = (size_t)o * v;
-      check_finite(sys->eps, (size_t)o + v, "eps");
-      check_finite(sys->B_oo, (size_t)X * o * o, "B_oo");
-      check_finite(sys->B_ov, (size_t)X * N, "B_ov");
-      check_finite(sys->B_vv, (size_t)X * v * v, "B_vv");
-      if (sys->dip) check_finite(sys->dip, 3 * N, "dip");
-      for (int i = 0; i + 1 < o; ++i)
-        if (sys->eps[i] > sys->eps[i + 1]) throw ppw::InvalidArg("occupied energies must be ascending");
-      if (sys->eps[o - 1] >= sys->eps[o]) throw ppw::InvalidArg("occupied energies must lie below virtual ones");
-    }
+    if (!sys->device_ptrs) ppw::check_host_system(*sys);
     ppw::SetupParams p;
     p.o = o;
     p.v = v;
@@ -184,15 +137,7 @@ pp_status pp_window_solve(pp_handle* h, double omega0, int32_t n_roots, double* 
       throw ppw::InvalidArg("n_roots out of range");
     if (!energies) throw ppw::InvalidArg("energies must not be NULL");
     if (osc && !h->ctx->dip) throw ppw::InvalidArg("oscillator strengths need dipole integrals at setup");
-    ppw::SolveOptions so;
-    so.precision = h->opt.precision;
-    so.tol = h->opt.tol;
-    so.block = h->opt.block;
-    so.krylov_steps = h->opt.krylov_steps;
-    so.max_basis = h->opt.max_basis;
-    so.max_cycles = h->opt.max_cycles;
-    so.d_clamp = h->opt.d_clamp;
-    so.seed = h->opt.seed;
+    const ppw::SolveOptions so = ppw::solve_options(h->opt);
     ppw::window_solve(*h->ctx, so, omega0, n_roots, energies, vectors, osc, info);
   });
 }
@@ -207,15 +152,7 @@ pp_status pp_window_solve_batch(pp_handle* h, int32_t n_windows, const double* o
       if (!std::isfinite(omega0[w])) throw ppw::InvalidArg("omega0 must be finite");
     if (n_roots < 1 || n_roots > PP_MAX_ROOTS || n_roots > h->ctx->N) throw ppw::InvalidArg("n_roots out of range");
     if (osc && !h->ctx->dip) throw ppw::InvalidArg("oscillator strengths need dipole integrals at setup");
-    ppw::SolveOptions so;
-    so.precision = h->opt.precision;
-    so.tol = h->opt.tol;
-    so.block = h->opt.block;
-    so.krylov_steps = h->opt.krylov_steps;
-    so.max_basis = h->opt.max_basis;
-    so.max_cycles = h->opt.max_cycles;
-    so.d_clamp = h->opt.d_clamp;
-    so.seed = h->opt.seed;
+    const ppw::SolveOptions so = ppw::solve_options(h->opt);
     ppw::window_solve_many(*h->ctx, so, n_windows, omega0, n_roots, energies, vectors, osc, info);
   });
 }
@@ -268,6 +205,7 @@ const char* pp_status_string(pp_status s) {
     case PP_EUNSTABLE: return "PP_EUNSTABLE: response matrix not positive definite";
     case PP_EDEVICE: return "PP_EDEVICE: HIP runtime error";
     case PP_ENOTSUP: return "PP_ENOTSUP: not supported";
+    case PP_EPENDING: return "PP_EPENDING: request not finished";
   }
   return "unknown status";
 }
@@ -317,6 +255,51 @@ pp_status ppint_gemm(int32_t fp32, int32_t M, int32_t N, int32_t K, int32_t KB, 
   });
   if (ws) (void)hipFree(ws);
   return st;
+}
+
+pp_status ppint_gemm_group(int32_t fp32, int32_t n, const ppint_gemm_member* m, int32_t* grouped_launches) {
+  std::string err;
+  return guarded(&err, [&] {
+    if (n < 1 || !m) throw ppw::InvalidArg("ppint_gemm_group: no members");
+    auto desc = [](const ppint_gemm_member& x) {
+      ppw::GemmDesc d;
+      d.M = x.M;
+      d.N = x.N;
+      d.K = x.K;
+      d.transA = x.transA;
+      d.transB = x.transB;
+      d.lda = x.lda;
+      d.ldb = x.ldb;
+      d.ldc = x.ldc;
+      return d;
+    };
+    int g = 0;
+    if (fp32) {
+      std::vector<ppw::GemmCall<float>> calls(n);
+      for (int i = 0; i < n; ++i) {
+        calls[i].d = desc(m[i]);
+        calls[i].alpha = (float)m[i].alpha;
+        calls[i].beta = (float)m[i].beta;
+        calls[i].A = (const float*)m[i].A;
+        calls[i].B = (const float*)m[i].B;
+        calls[i].C = (float*)m[i].C;
+      }
+      g = ppw::gemm_group_f32(calls, nullptr);
+    } else {
+      std::vector<ppw::GemmCall<double>> calls(n);
+      for (int i = 0; i < n; ++i) {
+        calls[i].d = desc(m[i]);
+        calls[i].alpha = m[i].alpha;
+        calls[i].beta = m[i].beta;
+        calls[i].A = (const double*)m[i].A;
+        calls[i].B = (const double*)m[i].B;
+        calls[i].C = (double*)m[i].C;
+      }
+      g = ppw::gemm_group_f64(calls, nullptr);
+    }
+    PPW_HIP(hipDeviceSynchronize());
+    if (grouped_launches) *grouped_launches = g;
+  });
 }
 
 pp_status ppint_syev(int32_t n, const double* A, double* w, double* Z) {

@@ -1,6 +1,8 @@
 // Shared declarations of the ppwin HIP library (gfx950 / CDNA4 only).
 #pragma once
 
+#include <vector>
+
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -80,6 +82,25 @@ void gemm_f32_hhat(const GemmDesc& d, float alpha, const float* A, const float* 
                    hipStream_t s, Workspace ws = {});
 
 // Algorithmic flop count of a GemmDesc (2 per multiply-add).
+// One GEMM of a set issued together (C = alpha op(A) op(B) + beta C); tag 1 selects the
+// kernel symbol of the amplitude contraction.  ws is the member's split-K workspace
+// for when it is launched on its own.
+template <typename T>
+struct GemmCall {
+  GemmDesc d;
+  T alpha = T(1), beta = T(0);
+  const T* A = nullptr;
+  const T* B = nullptr;
+  T* C = nullptr;
+  Workspace ws;
+  int tag = 0;
+};
+
+// Independent GEMMs (no member reads what another writes) on one stream, merged into
+// grouped launches by tile shape.  Returns the number of grouped launches made.
+int gemm_group_f64(const std::vector<GemmCall<double>>& calls, hipStream_t s);
+int gemm_group_f32(const std::vector<GemmCall<float>>& calls, hipStream_t s);
+
 inline double gemm_flops(const GemmDesc& d) {
   return 2.0 * d.M * (double)d.N * d.K * d.KB * d.nb1 * d.nb2;
 }

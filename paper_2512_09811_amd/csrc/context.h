@@ -215,6 +215,33 @@ void sigma_core(Context& c, int order, int k, const double* V, double* AV, doubl
 // Same products with the contractions on FP32 matrix cores (V and outputs FP64).
 void sigma_core_f32(Context& c, int order, int k, const double* V, double* AV, double* BV, double* SV);
 
+// One system's share of a merged product pass.
+struct PassJob {
+  Context* c = nullptr;
+  int order = 0;
+  int k = 0;
+  int prec = 0;  // 0: FP64 contractions, 1: FP32 contractions (FP64 assembly)
+  const double* V = nullptr;
+  double *AV = nullptr, *BV = nullptr, *SV = nullptr;
+};
+
+// Products of several systems (distinct contexts) in one pass on stream s: every
+// contraction step is issued for all systems together, its GEMMs merged into grouped
+// launches.  Each context's workspace must already hold its k vectors
+// (sigma_reserve); inputs must be ready on s.  Returns the number of grouped GEMM
+// launches issued (steps whose GEMMs were too small to fill the chip together are
+// launched one by one).
+int sigma_group(const std::vector<PassJob>& jobs, hipStream_t s);
+
+// Device bytes of a context for the given shape and policy: during setup (amplitude
+// strips included) and afterwards with product workspaces for k vectors (FP64, plus
+// FP32 when want_f32).  Upper bounds of what setup_context and sigma_reserve allocate.
+struct Footprint {
+  size_t setup_peak, steady;
+};
+Footprint context_footprint(int o, int v, int naux, int order, bool dip, bool store, int strip_rows, bool want_f32,
+                            int k);
+
 // Grows the product workspace to k vectors ahead of time (no allocation in the loop).
 void sigma_reserve(Context& c, int k, int precision);
 

@@ -20,6 +20,7 @@
 #include "common.h"
 
 #include <algorithm>
+#include <vector>
 
 namespace ppw {
 namespace {
@@ -80,10 +81,12 @@ __device__ __forceinline__ void tile_coords(int id, int tiles_m, int tiles_n, in
 //    sit 32 banks apart, writes are consecutive.
 // TAG only distinguishes kernel symbols (the amplitude contraction gets its own,
 // so that profiles can attribute its time); the code is identical.
-template <typename T, int BM, int BN, int BK, bool AK, bool BKC, int TAG>
-__global__ __launch_bounds__(kThreads, 2) void gemm_kernel(GemmDesc d, T alpha, const T* __restrict__ A,
-                                                        const T* __restrict__ B, T beta, T* __restrict__ C,
-                                                        T* __restrict__ W, int splitk) {
+// One workgroup's tile of C (or, with W, of split 'split' of its reduction) for the
+// flattened (batch, tile) index 'flat' of GEMM d.
+template <typename T, int BM, int BN, int BK, bool AK, bool BKC>
+__device__ __forceinline__ void gemm_tile(const GemmDesc& d, T alpha, const T* __restrict__ A,
+                                          const T* __restrict__ B, T beta, T* __restrict__ C, T* __restrict__ W,
+                                          int splitk, long flat, int split) {
   using acc_t = typename Mfma<T>::acc_t;
   constexpr int PK = 2;   // pad of k-contiguous tiles
   constexpr int PM = 16;  // pad of m/n-contiguous tiles
@@ -107,13 +110,11 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_kernel(GemmDesc d, T alpha, 
   const int tiles_m = (d.M + BM - 1) / BM;
   const int tiles_n = (d.N + BN - 1) / BN;
   const long ntiles = (long)tiles_m * tiles_n;
-  const long flat = xcd_remap(blockIdx.x, (long)gridDim.x);
   const int batch = (int)(flat / ntiles);
   int tm, tn;
   tile_coords((int)(flat % ntiles), tiles_m, tiles_n, tm, tn);
   const int m0 = tm * BM, n0 = tn * BN;
   const int b1 = batch / d.nb2, b2 = batch % d.nb2;
-  const int split = blockIdx.y;
 
   const T* Ab = A + b1 * d.sA1 + b2 * d.sA2;
   const T* Bb = B + b1 * d.sB1 + b2 * d.sB2;
@@ -228,6 +229,44 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_kernel(GemmDesc d, T alpha, 
       }
 }
 
+template <typename T, int BM, int BN, int BK, bool AK, bool BKC, int TAG>
+__global__ __launch_bounds__(kThreads, 2) void gemm_kernel(GemmDesc d, T alpha, const T* __restrict__ A,
+                                                        const T* __restrict__ B, T beta, T* __restrict__ C,
+                                                        T* __restrict__ W, int splitk) {
+  gemm_tile<T, BM, BN, BK, AK, BKC>(d, alpha, A, B, beta, C, W, splitk, xcd_remap(blockIdx.x, (long)gridDim.x),
+                                    blockIdx.y);
+}
+
+// Up to kGroupMax independent GEMMs of one tile shape in one grid: member g owns the
+// flattened workgroup ids [start_g, start_{g+1}).  The member is found by a
+// wave-uniform scan of the start table, so every member keeps the single-GEMM tile
+// schedule (and the XCD remap applies over the whole grid).
+constexpr int kGroupMax = 8;
+template <typename T>
+struct GroupMember {
+  GemmDesc d;
+  const T* A;
+  const T* B;
+  T* C;
+  T alpha, beta;
+  long start;
+};
+template <typename T>
+struct GroupArgs {
+  GroupMember<T> m[kGroupMax];
+  int n;
+};
+
+template <typename T, int BM, int BN, int BK, bool AK, bool BKC, int TAG>
+__global__ __launch_bounds__(kThreads, 2) void gemm_group_kernel(GroupArgs<T> g) {
+  const long flat = xcd_remap(blockIdx.x, (long)gridDim.x);
+  int j = 0;
+  for (int q = 1; q < g.n; ++q)
+    if (flat >= g.m[q].start) j = q;
+  const GroupMember<T>& mb = g.m[__builtin_amdgcn_readfirstlane(j)];
+  gemm_tile<T, BM, BN, BK, AK, BKC>(mb.d, mb.alpha, mb.A, mb.B, mb.beta, mb.C, nullptr, 1, flat - mb.start, 0);
+}
+
 template <typename T>
 __global__ void splitk_reduce_kernel(GemmDesc d, T alpha, T beta, const T* __restrict__ W, T* __restrict__ C,
                                      int splitk) {
@@ -250,15 +289,24 @@ __global__ void splitk_reduce_kernel(GemmDesc d, T alpha, T beta, const T* __res
 
 inline bool ntiles_total_exceeds(long n) { return n <= 0 || n > 2147483647L; }
 
+// Workgroups of one GEMM at tile shape BM x BN (before split-K); checks the limits
+// the kernel relies on.
+template <int BM, int BN, int BK>
+long checked_workgroups(const GemmDesc& d) {
+  const long nbatch = (long)d.nb1 * d.nb2;
+  const long wgs = (long)((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN) * nbatch;
+  if (ntiles_total_exceeds(wgs)) throw InvalidArg("gemm: too many workgroups");
+  // per-tile element offsets are 32-bit inside the kernel
+  if ((double)d.lda * std::max(BM, BK) + d.K >= 2147483647.0 || (double)d.ldb * std::max(BN, BK) + d.K >= 2147483647.0)
+    throw InvalidArg("gemm: leading dimension too large for 32-bit tile offsets");
+  return wgs;
+}
+
 template <typename T, int BM, int BN, int BK, bool AK, bool BKC, int TAG>
 void launch(const GemmDesc& d, T alpha, const T* A, const T* B, T beta, T* C, hipStream_t s, Workspace ws) {
   const int tiles_m = (d.M + BM - 1) / BM, tiles_n = (d.N + BN - 1) / BN;
   const long nbatch = (long)d.nb1 * d.nb2;
-  if (ntiles_total_exceeds((long)((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN) * nbatch))
-    throw InvalidArg("gemm: too many workgroups");
-  // per-tile element offsets are 32-bit inside the kernel
-  if ((double)d.lda * std::max(BM, BK) + d.K >= 2147483647.0 || (double)d.ldb * std::max(BN, BK) + d.K >= 2147483647.0)
-    throw InvalidArg("gemm: leading dimension too large for 32-bit tile offsets");
+  checked_workgroups<BM, BN, BK>(d);
   const long ntiles = (long)tiles_m * tiles_n;
   const int nkt = (d.K + BK - 1) / BK;
   const long total = (long)d.KB * nkt;
@@ -314,7 +362,104 @@ void gemm_dispatch(const GemmDesc& d, T alpha, const T* A, const T* B, T beta, T
 #undef PPW_GEMM_CASE
 }
 
+// One grouped launch of n <= kGroupMax members sharing the tile shape.
+template <typename T, int BM, int BN, int BK, bool AK, bool BKC, int TAG>
+void launch_group(const GemmCall<T>* const* calls, int n, hipStream_t s) {
+  GroupArgs<T> g{};
+  long total = 0;
+  for (int i = 0; i < n; ++i) {
+    const GemmCall<T>& c = *calls[i];
+    g.m[i] = GroupMember<T>{c.d, c.A, c.B, c.C, c.alpha, c.beta, total};
+    total += checked_workgroups<BM, BN, BK>(c.d);
+  }
+  g.n = n;
+  if (ntiles_total_exceeds(total)) throw InvalidArg("gemm: too many workgroups in a group");
+  gemm_group_kernel<T, BM, BN, BK, AK, BKC, TAG><<<dim3((unsigned)total), kThreads, 0, s>>>(g);
+  PPW_LAUNCH_CHECK();
+}
+
+template <typename T, int TAG>
+void group_dispatch(bool big, bool ak, bool bk, const GemmCall<T>* const* calls, int n, hipStream_t s) {
+#define PPW_GROUP_CASE(BMv, BNv, AKv, BKv)                              \
+  if (ak == AKv && bk == BKv) {                                         \
+    launch_group<T, BMv, BNv, 16, AKv, BKv, TAG>(calls, n, s);          \
+    return;                                                             \
+  }
+  if (big) {
+    PPW_GROUP_CASE(128, 128, true, true)
+    PPW_GROUP_CASE(128, 128, true, false)
+    PPW_GROUP_CASE(128, 128, false, true)
+    PPW_GROUP_CASE(128, 128, false, false)
+  } else {
+    PPW_GROUP_CASE(64, 64, true, true)
+    PPW_GROUP_CASE(64, 64, true, false)
+    PPW_GROUP_CASE(64, 64, false, true)
+    PPW_GROUP_CASE(64, 64, false, false)
+  }
+#undef PPW_GROUP_CASE
+}
+
+template <typename T>
+void single_dispatch(const GemmCall<T>& c, hipStream_t s) {
+  if (c.tag == 1)
+    gemm_dispatch<T, 1>(c.d, c.alpha, c.A, c.B, c.beta, c.C, s, c.ws);
+  else
+    gemm_dispatch<T, 0>(c.d, c.alpha, c.A, c.B, c.beta, c.C, s, c.ws);
+}
+
+// Independent GEMMs issued together: members with the same tile shape (and symbol
+// tag) go into grouped launches when together they fill the chip without split-K;
+// the rest (a lone member, or a set too small to fill 256 CUs) are launched one by
+// one, where split-K applies.
+template <typename T>
+int gemm_group_impl(const std::vector<GemmCall<T>>& calls, hipStream_t s) {
+  int grouped = 0;
+  struct Key {
+    bool big, ak, bk;
+    int tag;
+    bool operator==(const Key& o) const { return big == o.big && ak == o.ak && bk == o.bk && tag == o.tag; }
+  };
+  std::vector<Key> keys;
+  std::vector<std::vector<const GemmCall<T>*>> sets;
+  for (const auto& c : calls) {
+    const GemmDesc& d = c.d;
+    if (d.M <= 0 || d.N <= 0 || d.nb1 <= 0 || d.nb2 <= 0) continue;
+    if (d.K <= 0 || d.KB <= 0) throw InvalidArg("gemm: empty reduction");
+    const Key k{d.M >= 96 && d.N >= 96, d.transA == 0, d.transB != 0, c.tag};
+    size_t i = 0;
+    while (i < keys.size() && !(keys[i] == k)) ++i;
+    if (i == keys.size()) {
+      keys.push_back(k);
+      sets.emplace_back();
+    }
+    sets[i].push_back(&c);
+  }
+  for (size_t i = 0; i < keys.size(); ++i) {
+    const Key& k = keys[i];
+    auto& set = sets[i];
+    long wgs = 0;
+    for (auto* c : set)
+      wgs += k.big ? checked_workgroups<128, 128, 16>(c->d) : checked_workgroups<64, 64, 16>(c->d);
+    if (set.size() == 1 || wgs < 512) {
+      for (auto* c : set) single_dispatch(*c, s);
+      continue;
+    }
+    for (size_t j = 0; j < set.size(); j += kGroupMax) {
+      const int n = (int)std::min<size_t>(kGroupMax, set.size() - j);
+      if (k.tag == 1)
+        group_dispatch<T, 1>(k.big, k.ak, k.bk, set.data() + j, n, s);
+      else
+        group_dispatch<T, 0>(k.big, k.ak, k.bk, set.data() + j, n, s);
+      ++grouped;
+    }
+  }
+  return grouped;
+}
+
 }  // namespace
+
+int gemm_group_f64(const std::vector<GemmCall<double>>& calls, hipStream_t s) { return gemm_group_impl(calls, s); }
+int gemm_group_f32(const std::vector<GemmCall<float>>& calls, hipStream_t s) { return gemm_group_impl(calls, s); }
 
 void gemm_f64(const GemmDesc& d, double alpha, const double* A, const double* B, double beta, double* C,
               hipStream_t s, Workspace ws) {

@@ -24,6 +24,7 @@
 // rebuilt from B^ov (K = naux) and the denominators.
 #include <algorithm>
 #include <cmath>
+#include <functional>
 #include <vector>
 
 #include "context.h"
@@ -360,20 +361,76 @@ Ops<float> ops32(Context& c) {
                     c.Eo32, c.w32_c, c.w32_G, c.w32_U, c.w32_H, c.w32_S, c.w32_tau};
 }
 
+// A product pass as a sequence of steps: launched as they are issued, or recorded
+// (tape) so that the passes of several systems can be replayed in lockstep with the
+// GEMMs of one step merged into grouped launches.
+struct Step {
+  int kind = 2;  // 0: FP64 GEMM, 1: FP32 GEMM, 2: any other launch
+  GemmCall<double> g64;
+  GemmCall<float> g32;
+  std::function<void(hipStream_t)> fn;
+};
+
+template <typename T>
+struct Emit {
+  hipStream_t s = nullptr;
+  std::vector<Step>* tape = nullptr;
+  void gemm(const GemmDesc& d, T a, const T* A, const T* B, T b, T* C, Workspace ws, int tag = 0) {
+    if (!tape) {
+      if (tag == 1)
+        gemm_hhat_t<T>(d, a, A, B, b, C, s, ws);
+      else
+        gemm_t<T>(d, a, A, B, b, C, s, ws);
+      return;
+    }
+    Step st;
+    GemmCall<T> g;
+    g.d = d;
+    g.alpha = a;
+    g.beta = b;
+    g.A = A;
+    g.B = B;
+    g.C = C;
+    g.ws = ws;
+    g.tag = tag;
+    put(st, g);
+    tape->push_back(std::move(st));
+  }
+  void call(std::function<void(hipStream_t)> f) {
+    if (!tape) {
+      f(s);
+      return;
+    }
+    Step st;
+    st.fn = std::move(f);
+    tape->push_back(std::move(st));
+  }
+
+ private:
+  static void put(Step& st, const GemmCall<double>& g) {
+    st.kind = 0;
+    st.g64 = g;
+  }
+  static void put(Step& st, const GemmCall<float>& g) {
+    st.kind = 1;
+    st.g32 = g;
+  }
+};
+
 // Every contraction of the product (see the file comment): AV <- -K_A(V) [+0],
 // BV <- -K_B(V) - ring terms + ladder/ring-K terms, J, P1..P4 (delta-type
 // intermediates).  The diagonal term and the final combination are done in FP64
 // by sigma_assemble.
 template <typename T>
-void contract(Context& c, const Ops<T>& t, int order, int k, const T* V, T* AV, T* BV, T* J, T* P1, T* P2, T* P3,
-              T* P4) {
-  hipStream_t s = c.stream;
+void contract(Context& c, const Ops<T>& t, Emit<T>& e, int order, int k, const T* V, T* AV, T* BV, T* J, T* P1,
+              T* P2, T* P3, T* P4) {
+  hipStream_t s = e.s;
   const int o = c.o, v = c.v, X = c.naux;
   const long N = c.N;
   const T one = T(1), zero = T(0), mone = T(-1);
   // J: c[P][q] = sum_ia Bov[P][ia] V[q][ia];  J[q][ia] = sum_P c[P][q] Bov[P][ia]
-  gemm_t<T>(gd(X, k, (int)N, 0, N, 1, N, k), one, t.Bov, V, zero, t.c, s, c.ws);
-  gemm_t<T>(gd(k, (int)N, X, 1, k, 0, N, N), one, t.c, t.Bov, zero, J, s, c.ws);
+  e.gemm(gd(X, k, (int)N, 0, N, 1, N, k), one, t.Bov, V, zero, t.c, c.ws);
+  e.gemm(gd(k, (int)N, X, 1, k, 0, N, N), one, t.c, t.Bov, zero, J, c.ws);
   // G1[q][P][j][d] = sum_b V[q][j][b] Bvv[P][b][d]
   {
     GemmDesc d = gd(o, v, v, 0, v, 0, v, v);
@@ -383,7 +440,7 @@ void contract(Context& c, const Ops<T>& t, int order, int k, const T* V, T* AV, 
     d.sB2 = (long)v * v;
     d.sC1 = (long)X * N;
     d.sC2 = N;
-    gemm_t<T>(d, one, V, t.Bvv, zero, t.G, s, c.ws);
+    e.gemm(d, one, V, t.Bvv, zero, t.G, c.ws);
   }
   // AV = -K_A(V) = -sum_P Boo_P G1_P
   {
@@ -394,19 +451,19 @@ void contract(Context& c, const Ops<T>& t, int order, int k, const T* V, T* AV, 
     d.nb1 = k;
     d.sB1 = (long)X * N;
     d.sC1 = N;
-    gemm_t<T>(d, mone, t.Boo, t.G, zero, AV, s, c.ws);
+    e.gemm(d, mone, t.Boo, t.G, zero, AV, c.ws);
   }
   // U[(q,j)][(s,P,i)] = sum_b V[(q,j)][b] BovLam[(s,P,i)][b];  BV = -sum U R
   const int ns = order >= 2 ? 2 : 1;
   {
     const long Ucols = (long)ns * X * o;
-    gemm_t<T>(gd(k * o, (int)Ucols, v, 0, v, 1, v, Ucols), one, V, t.BovLam, zero, t.U, s, c.ws);
+    e.gemm(gd(k * o, (int)Ucols, v, 0, v, 1, v, Ucols), one, V, t.BovLam, zero, t.U, c.ws);
     if (ns == c.ns) {
       GemmDesc d = gd(o, v, o * ns * X, 1, o, 0, v, v);
       d.nb1 = k;
       d.sA1 = (long)o * Ucols;
       d.sC1 = N;
-      gemm_t<T>(d, mone, t.U, t.R, zero, BV, s, c.ws);
+      e.gemm(d, mone, t.U, t.R, zero, BV, c.ws);
     } else {
       // first-order product on a second-order handle: K_B(V) = sum_(j,P) U[q][(j,P)][i] Bov[P][j][a],
       // with R[j][1][P][a] = Bov[P][j][a] (outer loop over j, inner P)
@@ -417,7 +474,7 @@ void contract(Context& c, const Ops<T>& t, int order, int k, const T* V, T* AV, 
       d.nb1 = k;
       d.sA1 = (long)o * Ucols;
       d.sC1 = N;
-      gemm_t<T>(d, mone, t.U, t.R + (size_t)X * v, zero, BV, s, c.ws);
+      e.gemm(d, mone, t.U, t.R + (size_t)X * v, zero, BV, c.ws);
     }
   }
   if (order < 2) return;
@@ -430,7 +487,7 @@ void contract(Context& c, const Ops<T>& t, int order, int k, const T* V, T* AV, 
     d.sB1 = N;
     d.sC1 = (long)X * N;
     d.sC2 = N;
-    gemm_t<T>(d, mone, t.Boo, V, one, t.G, s, c.ws);
+    e.gemm(d, mone, t.Boo, V, one, t.G, c.ws);
   }
   const long kX = (long)k * X;
   auto outputs = [&](const T* H, int i0, int ib) {
@@ -443,7 +500,7 @@ void contract(Context& c, const Ops<T>& t, int order, int k, const T* V, T* AV, 
       d.nb1 = k;
       d.sA1 = X;
       d.sC1 = N;
-      gemm_t<T>(d, one, H, t.Bvv, one, BV + (size_t)i0 * v, s, c.ws);
+      e.gemm(d, one, H, t.Bvv, one, BV + (size_t)i0 * v, c.ws);
     }
     // BV[q][i][a] -= sum_(kk,P) Boo[P][i][kk] H[(kk,a)][(q,P)]   kk in i0..i0+ib-1
     {
@@ -454,16 +511,16 @@ void contract(Context& c, const Ops<T>& t, int order, int k, const T* V, T* AV, 
       d.nb1 = k;
       d.sB1 = X;
       d.sC1 = N;
-      gemm_t<T>(d, mone, t.Boo_t + (size_t)i0 * X, H, one, BV, s, c.ws);
+      e.gemm(d, mone, t.Boo_t + (size_t)i0 * X, H, one, BV, c.ws);
     }
   };
   double hflops = 0.0;
   if (t.tau) {
     // H[(i,c)][(q,P)] = sum_(j,d) tau[(i,c)][(j,d)] G[(q,P)][(j,d)]
     GemmDesc d = gd((int)N, (int)kX, (int)N, 0, N, 1, N, kX);
-    const int ev = c.events.start(s);
-    gemm_hhat_t<T>(d, one, t.tau, t.G, zero, t.H, s, c.ws);
-    c.events.stop(ev, s, 1);
+    const int ev = e.tape ? -1 : c.events.start(s);
+    e.gemm(d, one, t.tau, t.G, zero, t.H, c.ws, 1);
+    if (ev >= 0) c.events.stop(ev, s, 1);
     hflops += gemm_flops(d);
     c.stats.hhat_launches += 1;
     outputs(t.H, 0, o);
@@ -471,12 +528,17 @@ void contract(Context& c, const Ops<T>& t, int order, int k, const T* V, T* AV, 
     const int ib = c.strip_rows;
     for (int i0 = 0; i0 < o; i0 += ib) {
       const int nb = std::min(ib, o - i0);
-      gemm_t<T>(gd(nb * v, (int)N, X, 1, N, 0, N, N), one, t.Bov + (size_t)i0 * v, t.Bov, zero, t.S, s, c.ws);
-      tau_strip_t(t.S, o, v, i0, nb, c.eps_o, c.eps_v, t.tau_w, s);
+      e.gemm(gd(nb * v, (int)N, X, 1, N, 0, N, N), one, t.Bov + (size_t)i0 * v, t.Bov, zero, t.S, c.ws);
+      {
+        const T* Sst = t.S;
+        T* tw = t.tau_w;
+        const double *eo = c.eps_o, *evv = c.eps_v;
+        e.call([=](hipStream_t st) { tau_strip_t(Sst, o, v, i0, nb, eo, evv, tw, st); });
+      }
       GemmDesc d = gd(nb * v, (int)kX, (int)N, 0, N, 1, N, kX);
-      const int ev = c.events.start(s);
-      gemm_hhat_t<T>(d, one, t.tau_w, t.G, zero, t.H, s, c.ws);
-      c.events.stop(ev, s, 1);
+      const int ev = e.tape ? -1 : c.events.start(s);
+      e.gemm(d, one, t.tau_w, t.G, zero, t.H, c.ws, 1);
+      if (ev >= 0) c.events.stop(ev, s, 1);
       hflops += gemm_flops(d);
       c.stats.hhat_launches += 1;
       outputs(t.H, i0, nb);
@@ -484,19 +546,71 @@ void contract(Context& c, const Ops<T>& t, int order, int k, const T* V, T* AV, 
   }
   c.stats.hhat_flops += hflops;
   // delta-type terms: P1 = V Gv, P2 = V Ev, P3 = Go V, P4 = Eo V
-  gemm_t<T>(gd(k * o, v, v, 0, v, 0, v, v), one, V, t.Gv, zero, P1, s, c.ws);
-  gemm_t<T>(gd(k * o, v, v, 0, v, 0, v, v), one, V, t.Ev, zero, P2, s, c.ws);
+  e.gemm(gd(k * o, v, v, 0, v, 0, v, v), one, V, t.Gv, zero, P1, c.ws);
+  e.gemm(gd(k * o, v, v, 0, v, 0, v, v), one, V, t.Ev, zero, P2, c.ws);
   {
     GemmDesc d = gd(o, v, o, 0, o, 0, v, v);
     d.nb1 = k;
     d.sB1 = N;
     d.sC1 = N;
-    gemm_t<T>(d, one, t.Go, V, zero, P3, s, c.ws);
-    gemm_t<T>(d, one, t.Eo, V, zero, P4, s, c.ws);
+    e.gemm(d, one, t.Go, V, zero, P3, c.ws);
+    e.gemm(d, one, t.Eo, V, zero, P4, c.ws);
   }
 }
 
 }  // namespace
+
+Footprint context_footprint(int o, int v, int X, int order, bool dip, bool store, int strip_rows, bool want_f32,
+                            int k) {
+  // mirrors setup_context, grow_workspace and grow_workspace32 (arena blocks are
+  // rounded to 256 B)
+  auto r = [](size_t bytes) { return ((bytes + 255) / 256) * 256; };
+  const size_t D = sizeof(double), F = sizeof(float);
+  const size_t N = (size_t)o * v, K = (size_t)k;
+  const size_t ns = order >= 2 ? 2 : 1;
+  const int ib = order >= 2 ? std::max(1, std::min(strip_rows > 0 ? strip_rows : o, o)) : 0;
+  size_t keep = r(o * D) + r(v * D) + r(X * (size_t)o * o * D) + r(X * (size_t)v * v * D) + r(ns * X * N * D);
+  if (dip) keep += r(3 * N * D);
+  keep += r((size_t)o * o * X * D);
+  keep += r(std::max<size_t>((size_t)64 << 20, (size_t)X * 1024 * D));
+  keep += 3 * r(N * D);
+  size_t temp = 2 * r(N * D);  // diagonal integrals, freed after setup
+  if (order >= 2) {
+    keep += 2 * r((size_t)v * v * D) + 2 * r((size_t)o * o * D);
+    if (store) keep += r(N * N * D);
+    const size_t strip = (size_t)ib * v * N * D;
+    temp += (store ? 4 : 5) * r(strip);
+    temp += r((size_t)tau_blocks(o, v, ib) * ((o + ib - 1) / ib) * D) + r(D);
+  }
+  keep += r((size_t)o * ns * X * v * D);
+  if (want_f32 && order >= 1) {
+    keep += r(ns * X * N * F) + 2 * r((size_t)X * o * o * F) + r((size_t)X * v * v * F) + r((size_t)o * ns * X * v * F);
+    if (order >= 2) {
+      if (store) keep += r(N * N * F);
+      keep += 2 * r((size_t)v * v * F) + 2 * r((size_t)o * o * F);
+    }
+  }
+  // product workspaces
+  size_t ws = 0;
+  if (order >= 1) {
+    ws += r(K * N * D) + r(4 * K * N * D);
+    ws += r(X * K * D) + r(K * X * N * D) + r(K * o * ns * X * o * D);
+    const size_t ibw = store ? (size_t)o : (size_t)ib;
+    if (order >= 2) {
+      ws += r(ibw * v * K * X * D);
+      if (!store) ws += 2 * r((size_t)ib * v * N * D);
+    }
+    if (want_f32) {
+      ws += 4 * r(K * N * F) + r(4 * K * N * F);
+      ws += r(X * K * F) + r(K * X * N * F) + r(K * o * ns * X * o * F);
+      if (order >= 2) {
+        ws += r(ibw * v * K * X * F);
+        if (!store) ws += 2 * r((size_t)ib * v * N * F);
+      }
+    }
+  }
+  return Footprint{keep + temp, keep + ws};
+}
 
 void sigma_reserve(Context& c, int k, int precision) {
   if (c.order < 1) return;
@@ -506,60 +620,124 @@ void sigma_reserve(Context& c, int k, int precision) {
     grow_workspace(c, k);
 }
 
-void sigma_core(Context& c, int order, int k, const double* V, double* AV, double* BV, double* SV) {
+namespace {
+
+// One product pass of k vectors (contractions in the given precision, then the FP64
+// diagonal term and combination), launched on s or recorded on a tape.
+void emit_pass(Context& c, int order, int k, int prec, const double* V, double* AV, double* BV, double* SV,
+               hipStream_t s, std::vector<Step>* tape) {
+  const int o = c.o, v = c.v;
+  const long N = c.N, kN = (long)k * N;
+  const double *eo = c.eps_o, *ev = c.eps_v;
+  if (order == 0) {
+    Emit<double> em;
+    em.s = s;
+    em.tape = tape;
+    em.call([=](hipStream_t st) {
+      sigma_assemble(o, v, k, 0, eo, ev, V, nullptr, nullptr, nullptr, nullptr, nullptr, AV, BV, SV, st);
+    });
+    return;
+  }
+  double* J = c.w_J;
+  double* Q1 = c.w_P;
+  if (prec == 1) {
+    if (!c.BovLam32) throw NotSupported("FP32 products need precision = PP_FP32 at setup");
+    grow_workspace32(c, k);
+    J = c.w_J;
+    Q1 = c.w_P;
+    Emit<float> em;
+    em.s = s;
+    em.tape = tape;
+    float *V32 = c.w32_V, *AV32 = c.w32_AV, *BV32 = c.w32_BV, *J32 = c.w32_J, *P32 = c.w32_P;
+    em.call([=](hipStream_t st) { to_f32(kN, V, V32, st); });
+    contract<float>(c, ops32(c), em, order, k, V32, AV32, BV32, J32, P32, P32 + kN, P32 + 2 * kN, P32 + 3 * kN);
+    // the diagonal (orbital-energy) term and the combination stay in FP64
+    em.call([=](hipStream_t st) {
+      to_f64(kN, AV32, AV, st);
+      to_f64(kN, BV32, BV, st);
+      to_f64(kN, J32, J, st);
+      if (order >= 2) to_f64(4 * kN, P32, Q1, st);
+      sigma_assemble(o, v, k, order, eo, ev, V, J, Q1, Q1 + kN, Q1 + 2 * kN, Q1 + 3 * kN, AV, BV, SV, st);
+    });
+  } else {
+    grow_workspace(c, k);
+    J = c.w_J;
+    Q1 = c.w_P;
+    Emit<double> em;
+    em.s = s;
+    em.tape = tape;
+    contract<double>(c, ops64(c), em, order, k, V, AV, BV, J, Q1, Q1 + kN, Q1 + 2 * kN, Q1 + 3 * kN);
+    em.call([=](hipStream_t st) {
+      sigma_assemble(o, v, k, order, eo, ev, V, J, Q1, Q1 + kN, Q1 + 2 * kN, Q1 + 3 * kN, AV, BV, SV, st);
+    });
+  }
+}
+
+void pass_on_stream(Context& c, int order, int k, int prec, const double* V, double* AV, double* BV, double* SV) {
   if (order > c.order) throw InvalidArg("requested order exceeds the setup order");
   if (k <= 0) return;
   hipStream_t s = c.stream;
-  const int o = c.o, v = c.v;
-  const long N = c.N;
   if (order == 0) {
-    sigma_assemble(o, v, k, 0, c.eps_o, c.eps_v, V, nullptr, nullptr, nullptr, nullptr, nullptr, AV, BV, SV, s);
+    emit_pass(c, 0, k, prec, V, AV, BV, SV, s, nullptr);
     return;
   }
-  grow_workspace(c, k);
   if (c.events.pending() > 4096) c.resolve_stats();
   const int ev_pass = c.events.start(s);
-  double* P1 = c.w_P;
-  double* P2 = P1 + (size_t)k * N;
-  double* P3 = P2 + (size_t)k * N;
-  double* P4 = P3 + (size_t)k * N;
-  contract<double>(c, ops64(c), order, k, V, AV, BV, c.w_J, P1, P2, P3, P4);
-  sigma_assemble(o, v, k, order, c.eps_o, c.eps_v, V, c.w_J, P1, P2, P3, P4, AV, BV, SV, s);
+  emit_pass(c, order, k, prec, V, AV, BV, SV, s, nullptr);
   c.events.stop(ev_pass, s, 0);
   c.stats.flops += sigma_flops(c, order, k);
+  if (prec == 1) c.stats.flops32 += sigma_flops(c, order, k);
   c.stats.vectors += k;
 }
 
+}  // namespace
+
+void sigma_core(Context& c, int order, int k, const double* V, double* AV, double* BV, double* SV) {
+  pass_on_stream(c, order, k, 0, V, AV, BV, SV);
+}
+
 void sigma_core_f32(Context& c, int order, int k, const double* V, double* AV, double* BV, double* SV) {
-  if (order > c.order) throw InvalidArg("requested order exceeds the setup order");
-  if (k <= 0) return;
-  if (order >= 1 && !c.BovLam32) throw NotSupported("FP32 products need precision = PP_FP32 at setup");
-  hipStream_t s = c.stream;
-  const int o = c.o, v = c.v;
-  const long N = c.N;
-  if (order == 0) {
-    sigma_assemble(o, v, k, 0, c.eps_o, c.eps_v, V, nullptr, nullptr, nullptr, nullptr, nullptr, AV, BV, SV, s);
-    return;
+  pass_on_stream(c, order, k, 1, V, AV, BV, SV);
+}
+
+int sigma_group(const std::vector<PassJob>& jobs, hipStream_t s) {
+  std::vector<std::vector<Step>> tapes(jobs.size());
+  for (size_t j = 0; j < jobs.size(); ++j) {
+    const PassJob& pj = jobs[j];
+    for (size_t i = 0; i < j; ++i)
+      if (jobs[i].c == pj.c) throw InvalidArg("sigma_group: one pass per system (workspaces are per system)");
+    if (pj.order > pj.c->order) throw InvalidArg("requested order exceeds the setup order");
+    if (pj.k <= 0) continue;
+    emit_pass(*pj.c, pj.order, pj.k, pj.prec, pj.V, pj.AV, pj.BV, pj.SV, s, &tapes[j]);
+    if (pj.order >= 1) {
+      pj.c->stats.flops += sigma_flops(*pj.c, pj.order, pj.k);
+      if (pj.prec == 1) pj.c->stats.flops32 += sigma_flops(*pj.c, pj.order, pj.k);
+      pj.c->stats.vectors += pj.k;
+    }
   }
-  grow_workspace32(c, k);
-  if (c.events.pending() > 4096) c.resolve_stats();
-  const int ev_pass = c.events.start(s);
-  const long kN = (long)k * N;
-  to_f32(kN, V, c.w32_V, s);
-  float* P1 = c.w32_P;
-  contract<float>(c, ops32(c), order, k, c.w32_V, c.w32_AV, c.w32_BV, c.w32_J, P1, P1 + kN, P1 + 2 * kN,
-                  P1 + 3 * kN);
-  // the diagonal (orbital-energy) term and the combination stay in FP64
-  to_f64(kN, c.w32_AV, AV, s);
-  to_f64(kN, c.w32_BV, BV, s);
-  to_f64(kN, c.w32_J, c.w_J, s);
-  if (order >= 2) to_f64(4 * kN, c.w32_P, c.w_P, s);
-  double* Q1 = c.w_P;
-  sigma_assemble(o, v, k, order, c.eps_o, c.eps_v, V, c.w_J, Q1, Q1 + kN, Q1 + 2 * kN, Q1 + 3 * kN, AV, BV, SV, s);
-  c.events.stop(ev_pass, s, 0);
-  c.stats.flops += sigma_flops(c, order, k);
-  c.stats.flops32 += sigma_flops(c, order, k);
-  c.stats.vectors += k;
+  // lockstep replay: step p of every pass, GEMMs of one step merged by tile shape
+  size_t len = 0;
+  for (auto& t : tapes) len = std::max(len, t.size());
+  std::vector<GemmCall<double>> g64;
+  std::vector<GemmCall<float>> g32;
+  int grouped = 0;
+  for (size_t p = 0; p < len; ++p) {
+    g64.clear();
+    g32.clear();
+    for (auto& t : tapes) {
+      if (p >= t.size()) continue;
+      Step& st = t[p];
+      if (st.kind == 0)
+        g64.push_back(st.g64);
+      else if (st.kind == 1)
+        g32.push_back(st.g32);
+      else
+        st.fn(s);
+    }
+    if (!g64.empty()) grouped += gemm_group_f64(g64, s);
+    if (!g32.empty()) grouped += gemm_group_f32(g32, s);
+  }
+  return grouped;
 }
 
 }  // namespace ppw

@@ -4,6 +4,8 @@
 #include "../../include/ppwin.h"
 #include "context.h"
 
+#include <exception>
+
 namespace ppw {
 
 struct SolveOptions {
@@ -16,6 +18,38 @@ struct SolveOptions {
   double d_clamp = 1e-4;
   unsigned long long seed = 0;
 };
+
+// One window solve's request for A, B and S products of k orthonormal vectors V
+// ([k][N] on the device, ready when 'ready' completes); the sink writes AV, BV, SV
+// and records 'done' on the stream that wrote them.
+struct ProductRequest {
+  int id = 0;
+  int k = 0;
+  int prec = 0;  // 0: FP64 products, 1: FP32 contractions
+  Context* ctx = nullptr;
+  const double* V = nullptr;
+  double *AV = nullptr, *BV = nullptr, *SV = nullptr;
+  hipEvent_t ready = nullptr, done = nullptr;
+  bool served = false;
+  std::exception_ptr err;
+};
+
+// Where window solves send their product requests (blocking until served).
+class ProductSink {
+ public:
+  virtual ~ProductSink() = default;
+  virtual void multiply(ProductRequest& r) = 0;
+};
+
+// Largest number of vectors one window solve puts into a single product request.
+int window_block_vectors(long N, int n_roots, const SolveOptions& opt);
+// Device bytes one window solve allocates from its context's arena.
+size_t window_solve_bytes(long N, int n_roots, const SolveOptions& opt);
+
+// One window solve whose products go through 'sink' (shared with other solves).
+// The context's product workspace must already hold window_block_vectors vectors.
+void window_solve_shared(Context& c, const SolveOptions& opt, double omega0, int n_roots, ProductSink& sink, int id,
+                         double* energies, double* vectors, double* osc, pp_solve_info* info);
 
 // Roots of M z = omega Sigma z nearest omega0 (positive branch).  Host outputs.
 // Throws NotConverged after writing all outputs when max_cycles is reached.

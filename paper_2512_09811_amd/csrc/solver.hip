@@ -402,20 +402,13 @@ GemmDesc gd(int M, int N, int K, int tA, long lda, int tB, long ldb, long ldc) {
 // with a completion event per request.  Requests are served in window order, so the
 // batch composition (and therefore every rounding) is a deterministic function of
 // the inputs.
-class ProductBatcher {
+// Merges the product requests of the windows of one system into shared passes: a
+// pass runs when every window still solving has a request pending.
+class ProductBatcher : public ProductSink {
  public:
-  struct Req {
-    int id = 0;
-    int k = 0;
-    int prec = 0;  // 0: FP64 products, 1: FP32 contractions
-    const double* V = nullptr;
-    double *AV = nullptr, *BV = nullptr, *SV = nullptr;
-    hipEvent_t ready = nullptr, done = nullptr;
-    bool served = false;
-    std::exception_ptr err;
-  };
+  using Req = ProductRequest;
   ProductBatcher(Context& c, int active, int precision) : c_(c), active_(active), prec_(precision) {}
-  ~ProductBatcher() {
+  ~ProductBatcher() override {
     for (void* q : bufs_) c_.arena.free(q);
   }
   void reserve(int ktot) {
@@ -429,7 +422,7 @@ class ProductBatcher {
     sigma_reserve(c_, ktot, 0);
     if (prec_ == 1) sigma_reserve(c_, ktot, 1);
   }
-  void multiply(Req& r) {
+  void multiply(Req& r) override {
     std::unique_lock<std::mutex> lk(mu_);
     r.served = false;
     pending_.push_back(&r);
@@ -501,15 +494,30 @@ class ProductBatcher {
   int cap_ = 0;
 };
 
+// Block size, basis limit and vectors per extension of one window solve (as the
+// Solver constructor sets them).
+struct SolverDims {
+  int m, nbmax, kmax;
+};
+SolverDims solver_dims(long N, int nroots, const SolveOptions& o) {
+  SolverDims d;
+  d.m = o.block > 0 ? o.block : nroots + std::max(2, nroots / 2);
+  d.m = (int)std::min<long>(d.m, N);
+  d.nbmax = (int)std::min<long>(o.max_basis > 0 ? o.max_basis : 400, N);
+  d.nbmax = std::max(d.nbmax, std::min<int>((int)N, 2 * d.m));
+  d.kmax = 2 * d.m;
+  return d;
+}
+
+
 class Solver {
  public:
-  Solver(Context& c, const SolveOptions& o, double w0, int nroots, ProductBatcher* pb, int id)
+  Solver(Context& c, const SolveOptions& o, double w0, int nroots, ProductSink* pb, int id)
       : c_(c), opt_(o), w0_(w0), nr_(nroots), N_(c.N), pb_(pb), id_(id) {
-    m_ = o.block > 0 ? o.block : nroots + std::max(2, nroots / 2);
-    m_ = (int)std::min<long>(m_, N_);
-    nbmax_ = (int)std::min<long>(o.max_basis > 0 ? o.max_basis : 400, N_);
-    nbmax_ = std::max(nbmax_, std::min<int>((int)N_, 2 * m_));
-    kmax_ = 2 * m_;  // new vectors per extension (X and Y halves of a block)
+    const SolverDims dm = solver_dims(N_, nroots, o);
+    m_ = dm.m;
+    nbmax_ = dm.nbmax;
+    kmax_ = dm.kmax;  // new vectors per extension (X and Y halves of a block)
     trace_ = std::getenv("PPWIN_TRACE") != nullptr;
     PPW_HIP(hipStreamCreateWithFlags(&s_, hipStreamNonBlocking));
     PPW_HIP(hipEventCreateWithFlags(&ev_ready_, hipEventDisableTiming));
@@ -534,7 +542,7 @@ class Solver {
   int nr_, m_, nbmax_, kmax_;
   hipStream_t s_ = nullptr;
   long N_;
-  ProductBatcher* pb_;
+  ProductSink* pb_;
   int id_;
   hipEvent_t ev_ready_ = nullptr, ev_done_ = nullptr;
   bool trace_ = false;  // per-cycle progress on stderr when PPWIN_TRACE is set
@@ -676,8 +684,9 @@ class Solver {
   // A, B, S products of k orthonormal vectors X (device, [k][N]) into AV_, BV_, SV_,
   // merged with the other windows' requests by the batcher
   void products(int k, const double* X, bool exact) {
-    ProductBatcher::Req r;
+    ProductRequest r;
     r.id = id_;
+    r.ctx = &c_;
     r.k = k;
     r.prec = (exact || opt_.precision != 1 || refined_) ? 0 : 1;
     r.V = X;
@@ -1156,6 +1165,7 @@ void Solver::run(double* energies, double* vectors, double* osc, pp_solve_info* 
   if (!converged) throw NotConverged("window solve reached max_cycles before every root met the tolerance");
 }
 
+
 }  // namespace
 
 void window_solve_many(Context& c, const SolveOptions& opt, int nw, const double* omega0, int n_roots,
@@ -1215,6 +1225,44 @@ void window_solve_many(Context& c, const SolveOptions& opt, int nw, const double
 void window_solve(Context& c, const SolveOptions& opt, double omega0, int n_roots, double* energies,
                   double* vectors, double* osc, pp_solve_info* info) {
   window_solve_many(c, opt, 1, &omega0, n_roots, energies, vectors, osc, info);
+}
+
+
+int window_block_vectors(long N, int n_roots, const SolveOptions& opt) { return solver_dims(N, n_roots, opt).kmax; }
+
+size_t window_solve_bytes(long N, int n_roots, const SolveOptions& opt) {
+  // mirrors Solver::alloc (arena blocks are rounded to 256 B)
+  const SolverDims d = solver_dims(N, n_roots, opt);
+  auto r = [](size_t bytes) { return ((bytes + 255) / 256) * 256; };
+  const size_t D = sizeof(double);
+  const size_t bN = (size_t)d.nbmax * N, kN = (size_t)d.kmax * N;
+  const size_t bk = (size_t)d.nbmax * d.kmax, bb = (size_t)d.nbmax * d.nbmax, kk = (size_t)d.kmax * d.kmax;
+  size_t t = 12 * r(bN * D) + 10 * r(kN * D);
+  t += 2 * r(bk * D);                                   // c1, c2
+  t += 2 * r(std::max(kk, bb) * D);                     // gram, eigvec
+  t += r(d.nbmax * D);                                  // eigval
+  t += r(std::max(kk, bk) * D) + r(kk * D);             // T, R
+  t += r(bk * D) + r(kk * D);                           // C, R tot
+  t += 2 * r(std::max(bk, bb) * D);                     // tmp, tmp2
+  t += r(std::max(d.kmax, 8) * D);                      // norms
+  t += 6 * r(bk * D);                                   // cx, cy, cdx, cdy, cu, cw
+  t += r((size_t)8 * d.kmax * D) + r((size_t)d.kmax * D);  // stats, alpha
+  t += 9 * r(bb * D);                                   // Ap .. K
+  t += r(d.nbmax * D) + r(bb * D) + 2 * r(bb * D) + r(d.nbmax * D);  // theta2, Zk, us, ws, theta
+  t += r(std::max((size_t)2 * d.nbmax, (size_t)3 * 64) * D);
+  t += r(std::max((size_t)2 * std::max(bb, kk), partial_syev_scratch(d.nbmax, 64)) * D);
+  t += 2 * r(std::max(d.kmax, d.nbmax) * sizeof(int)) + r(4 * sizeof(int));
+  t += r((size_t)2 * d.m * N * D);                      // noise
+  t += r((size_t)32 << 20);                             // split-K workspace
+  return t;
+}
+
+void window_solve_shared(Context& c, const SolveOptions& opt, double omega0, int n_roots, ProductSink& sink, int id,
+                         double* energies, double* vectors, double* osc, pp_solve_info* info) {
+  PPW_HIP(hipSetDevice(c.device));
+  Solver sv(c, opt, omega0, n_roots, &sink, id);
+  PPW_HIP(hipStreamSynchronize(c.stream));
+  sv.run(energies, vectors, osc, info);
 }
 
 }  // namespace ppw

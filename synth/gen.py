@@ -127,15 +127,15 @@ def gen_config(name: str) -> System:
     return gen(c["seed"], c["o"], c["v"], c["naux"])
 
 
-def gen_request(r: int):
+def gen_request(r: int, o_min: int = 16, o_max: int = 128):
     """Serving-stream request r: its system and (omega0, n_roots).
 
-    n_occ ~ U{16..128}, n_vir = 4 n_occ, n_aux = 12 n_occ, omega0 ~ U[0.3, 1.5],
-    n_roots ~ U{4..12}; the request parameters are drawn first from the same
-    seeded stream as the system.
+    n_occ ~ U{o_min..o_max} (16..128 for the full stream), n_vir = 4 n_occ,
+    n_aux = 12 n_occ, omega0 ~ U[0.3, 1.5], n_roots ~ U{4..12}; the request
+    parameters are drawn first from the same seeded stream as the system.
     """
     rng = np.random.default_rng(REQUEST_SEED_BASE + r)
-    o = int(rng.integers(16, 129))
+    o = int(rng.integers(o_min, o_max + 1))
     omega = float(rng.uniform(0.3, 1.5))
     nroots = int(rng.integers(4, 13))
     sys_seed = int(rng.integers(0, 2**31 - 1))

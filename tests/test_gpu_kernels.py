@@ -105,3 +105,33 @@ def test_small_cholesky(B, n):
     L = torch.empty((n, n), dtype=torch.float64, device="cuda")
     B.cholesky(dA, L)
     np.testing.assert_allclose(L.cpu().numpy(), np.linalg.cholesky(A), rtol=0, atol=1e-12 * np.sqrt(n))
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_gemm_group(B, fp32):
+    """Independent GEMMs issued together (grouped launches across members of one tile
+    shape, single launches for the rest) equal their plain products."""
+    rng = np.random.default_rng(77)
+    dt = torch.float32 if fp32 else torch.float64
+    # (M, N, K, transA, transB): the first five share a shape class and fill the chip
+    # together (grouped); the 64-tile pair is too small and runs one by one
+    shapes = [(1500, 1400, 96, 0, 1), (1300, 1100, 61, 0, 1), (997, 1603, 130, 0, 1), (1200, 1200, 16, 0, 1),
+              (1100, 1300, 77, 0, 1), (1400, 1500, 40, 1, 0), (1024, 1301, 33, 1, 0), (1600, 1700, 30, 1, 0), (1400, 1300, 20, 1, 0),
+              (60, 70, 50, 0, 0), (33, 90, 21, 0, 0)]
+    members, refs = [], []
+    for M, N, K, tA, tB in shapes:
+        A = rng.standard_normal((K, M) if tA else (M, K))
+        Bm = rng.standard_normal((N, K) if tB else (K, N))
+        C0 = rng.standard_normal((M, N))
+        a = A.T if tA else A
+        b = Bm.T if tB else Bm
+        refs.append(0.75 * (a @ b) + 0.5 * C0)
+        members.append(dict(M=M, N=N, K=K, transA=tA, transB=tB, lda=A.shape[1], ldb=Bm.shape[1], ldc=N,
+                            A=torch.tensor(A, dtype=dt, device="cuda"), B=torch.tensor(Bm, dtype=dt, device="cuda"),
+                            C=torch.tensor(C0, dtype=dt, device="cuda"), alpha=0.75, beta=0.5))
+    g = B.gemm_group(members, fp32=fp32)
+    assert g >= 2  # both 128-tile shape classes went out as grouped launches
+    for m, ref, (M, N, K, tA, tB) in zip(members, refs, shapes):
+        got = m["C"].double().cpu().numpy()
+        tol = (2e-6 if fp32 else 1e-13) * np.sqrt(K) * 3
+        np.testing.assert_allclose(got, ref, rtol=0, atol=tol)
