@@ -31,6 +31,31 @@ PEAK_FP64_MFMA_TFLOPS = 78.6
 PEAK_FP32_MFMA_TFLOPS = 157.3
 HBM_TBPS = 8.0
 
+# HBM traffic of the amplitude contraction H = tau G at this workload (FP64, 4
+# windows), per launch, from two rocprofv3 --pmc runs of this script (FETCH_SIZE,
+# then WRITE_SIZE, KiB per dispatch) scaled by what the same counters read for a
+# plain 1 GiB device copy in the same runs (--copy-calibration).  The figures hold
+# for the GEMM source with this digest and for launches of this size only;
+# otherwise the roofline reports traffic as null.
+HHAT_TRAFFIC = {"gemm_sha256_16": "bcbea7abb7da1315", "flops_per_launch": 3735552000000.0,
+                "fetch_kib": 24121739.0, "write_kib": 2280000.0,
+                "copy_fetch_kib": 524316.0, "copy_write_kib": 1048576.0}
+
+
+def hhat_traffic(flops_per_launch, precision):
+    """Calibrated HBM bytes per launch of the amplitude contraction, or None."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_2512_09811_amd", "csrc", "gemm.hip")
+    with open(src, "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()[:16]
+    t = HHAT_TRAFFIC
+    if precision != "fp64" or digest != t["gemm_sha256_16"] or abs(flops_per_launch / t["flops_per_launch"] - 1) > 1e-9:
+        return None
+    kib = 1 << 20  # KiB in a GiB
+    fetch = t["fetch_kib"] * (kib / t["copy_fetch_kib"])
+    write = t["write_kib"] * (kib / t["copy_write_kib"])
+    return 1024.0 * (fetch + write)
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -41,6 +66,12 @@ def parse():
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--windows", type=int, default=0, help="use only the first N windows (profiling)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="end with three plain 1 GiB device copies (reference dispatches for HBM traffic counters)")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving stream instead of the batched-window workload (its own JSON line)")
+    ap.add_argument("--requests", type=int, default=48, help="serving: timed requests")
+    ap.add_argument("--occ", default="16,40", help="serving: n_occ range lo,hi (the full stream is 16,128)")
     return ap.parse_args()
 
 
@@ -70,12 +101,103 @@ def cpu_baseline(name):
                        f"diagonalisation, one diagonalisation serving all {len(omegas)} windows; {dt:.1f} s")
 
 
+def serve_main(args):
+    """Serving stream: requests drawn like the serving workload (n_vir = 4 n_occ,
+    n_aux = 12 n_occ, omega0 ~ U[0.3, 1.5], 4-12 roots), submitted to one pp_server.
+    A closed-loop warm-up (all warm-up requests at once) measures the saturated
+    throughput X; the timed stream then arrives as a Poisson process at 0.8 X.
+    Latency is submission -> result."""
+    import threading
+    import torch  # noqa: F401  (initializes the device runtime first)
+    import paper_2512_09811_amd as P
+    from synth.gen import gen_request
+    lo, hi = (int(x) for x in args.occ.split(","))
+    prec = P.PP_FP32 if args.precision == "fp32" else P.PP_FP64
+    nwarm = max(8, args.requests // 4)
+    t0 = time.perf_counter()
+    reqs = [gen_request(r, lo, hi) for r in range(nwarm + args.requests)]
+    print(f"[serve] generated {len(reqs)} requests in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    srv = P.Server(precision=prec)
+    # warm-up: saturated closed loop
+    t0 = time.perf_counter()
+    ids = [srv.submit_system(s_, w, nr) for s_, w, nr in reqs[:nwarm]]
+    for j, i in enumerate(ids):
+        srv.wait(i, allow_unconverged=True)
+        print(f"[serve] warm-up {j + 1}/{nwarm} done at {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    x_sat = nwarm / (time.perf_counter() - t0)
+    lam = 0.8 * x_sat
+    print(f"[serve] warm-up: {nwarm} requests, saturated {x_sat:.2f} solves/s; arrivals at {lam:.2f}/s",
+          file=sys.stderr, flush=True)
+    srv.reset_stats()
+    rng = np.random.default_rng(12345)
+    gaps = rng.exponential(1.0 / lam, args.requests)
+    timed = reqs[nwarm:]
+    ids = [None] * len(timed)
+
+    def client():
+        t_next = time.perf_counter()
+        for j, (s_, w, nr) in enumerate(timed):
+            t_next += gaps[j]
+            d = t_next - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            ids[j] = srv.submit_system(s_, w, nr)
+
+    t0 = time.perf_counter()
+    th = threading.Thread(target=client)
+    th.start()
+    th.join()
+    res = []
+    for j, i in enumerate(ids):
+        res.append(srv.wait(i, allow_unconverged=True))
+        if (j + 1) % 8 == 0:
+            print(f"[serve] {j + 1}/{len(ids)} results", file=sys.stderr, flush=True)
+    elapsed = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    conv = sum(1 for r in res if r["status"] == P.PP_OK and np.all(r["converged"] == 1))
+    lat = np.array([r["latency_seconds"] for r in res])
+    occ = [s_.o for s_, _, _ in timed]
+    line = {
+        "metric": "serving: window solves/sec with p50/p99 latency (Poisson arrivals at 0.8x saturated rate)",
+        "value": conv / elapsed,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.requests,
+        "warmup": nwarm,
+        "ms_per_step": 1e3 * elapsed / args.requests,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32",
+        "data": "synthetic (seeded serving stream)",
+        "config": {"workload": f"serving stream: {args.requests} requests, n_occ ~ U{{{lo}..{hi}}}, n_vir = 4 n_occ, "
+                               f"n_aux = 12 n_occ, omega0 ~ U[0.3,1.5], 4-12 roots, second order",
+                   "arrival_rate_per_s": lam, "saturated_rate_per_s": x_sat, "mean_n_occ": float(np.mean(occ))},
+        "windows_converged": f"{conv}/{len(res)}",
+        "latency_p50_s": float(np.percentile(lat, 50)),
+        "latency_p99_s": float(np.percentile(lat, 99)),
+        "queued_p50_s": st["queued_p50"],
+        "queued_p99_s": st["queued_p99"],
+        "passes": st["passes"],
+        "mean_requests_per_pass": st["mean_requests_per_pass"],
+        "grouped_launches": st["grouped_launches"],
+        "peak_running": st["peak_running"],
+        "sigma_tflops": st["product_flops"] / st["product_seconds"] / 1e12 if st["product_seconds"] > 0 else 0.0,
+        "sigma_fraction_of_time": st["product_seconds"] / elapsed,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is a design "
                                    "note, not implemented)"}))
         sys.exit(2)
+    if args.serve:
+        serve_main(args)
+        return
     import torch
     import paper_2512_09811_amd as P
     from synth.gen import CONFIGS, WINDOWS, gen_config
@@ -149,6 +271,10 @@ def main():
     value = ok / elapsed if golden is not None else n_windows / elapsed
     peak = PEAK_FP32_MFMA_TFLOPS if args.precision == "fp32" else PEAK_FP64_MFMA_TFLOPS
     achieved = (h_flops / h_sec) / 1e12 if h_sec > 0 else 0.0
+    # algorithmic bytes of one launch: tau (N x N) read once, G read and H written once
+    kX = (h_flops / max(h_n, 1)) / (2.0 * cfg["o"] * cfg["v"] * cfg["o"] * cfg["v"])
+    Nph = cfg["o"] * cfg["v"]
+    hhat_bytes = 8.0 * Nph * Nph + 16.0 * Nph * kX
     line = {
         "metric": "window solves/sec + sigma-build TFLOP/s at 1e-6 Ha; p50/p99 solve latency",
         "value": value,
@@ -176,8 +302,19 @@ def main():
         "roofline": {"bound": "mfma", "kernel": "gemm_kernel<double,128,128,16,1> (H = tau G)",
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                      "launches": h_n, "avg_launch_ms": 1e3 * h_sec / max(h_n, 1),
-                     "flops_per_launch": h_flops / max(h_n, 1), "traffic": None},
+                     "flops_per_launch": h_flops / max(h_n, 1),
+                     "traffic": hhat_traffic(h_flops / max(h_n, 1), args.precision),
+                     "algorithmic_bytes_per_launch": hhat_bytes},
     }
+    if args.copy_calibration:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters calibrate the
+        # traffic counters of the kernels above (1 GiB = 1048576 KiB each way)
+        x = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(name)
     print(json.dumps(line), flush=True)
