@@ -47,6 +47,13 @@ pp_status ppint_gemm_group(int32_t fp32, int32_t n, const ppint_gemm_member* mem
  * (row-major n x n, Z[r*n + c] = component r of vector c). */
 pp_status ppint_syev(int32_t n, const double* A, double* w, double* Z);
 
+/* The p eigenpairs of the symmetric n x n A (device, row-major) whose eigenvalues
+ * are nearest 'target', by the library's partial solver (tridiagonalization,
+ * bisection, inverse iteration, Rayleigh-Ritz in their span): lam[p] ascending,
+ * Z[n][p] row-major (column j = vector j).  *q = number of pairs found (<= p). */
+pp_status ppint_partial_syev(int32_t n, const double* A, double target, int32_t p, double* lam, double* Z,
+                             int32_t* q);
+
 /* Lower Cholesky factor of an SPD n x n matrix (device, row-major), in L. */
 pp_status ppint_cholesky(int32_t n, const double* A, double* L);
 

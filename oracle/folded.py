@@ -36,8 +36,15 @@ the paper leaves open:
   pairs are turned into corrections by the diagonal of the shifted pencil
   (a 2x2 solve per particle-hole pair in the (X+Y, X-Y) coordinates); they
   start the next cycle's Jacobi steps.  When the basis is full it is replaced
-  by the X+Y and X-Y parts of the block's Ritz vectors.  Converged when every
-  target root has |r| <= tol |y|.
+  by the X+Y and X-Y parts of the block's Ritz vectors.
+* Completeness (the paper does not say when a window is finished).  Ritz
+  extraction is unreliable for interior eigenvalues: an eigenvector that is
+  almost entirely in the subspace can appear as a polluted Ritz pair next to
+  omega0 with a large residual and a large folded quotient, and spurious Ritz
+  values appear there too.  So the window is converged only when every Ritz
+  pair whose value lies within the farthest target's distance of omega0 has
+  |r| <= tol |y|; those pairs lead the block, so they are corrected and kept
+  at restarts, and the result is the n_roots of them nearest omega0.
 """
 from __future__ import annotations
 
@@ -222,14 +229,25 @@ def folded_window_solve(A, B, S, omega0, n_roots, *, block=None, krylov_steps=2,
         fw = MW - omega0 * SU
         folded = 0.5 * (np.sum(fu * fu, 0) + np.sum(fw * fw, 0)) / ynorm ** 2
         order = np.argsort(folded, kind="stable")
-        blk = order[:m]
         tgt = order[:n_roots]
+        # every Ritz value within the farthest target's distance of omega0 must
+        # converge as well; those pairs lead the block (see the module docstring)
+        dmax = np.abs(th[tgt] - omega0).max()
+        inner = np.where(np.abs(th - omega0) <= dmax * (1 + 1e-12))[0]
+        inner = inner[np.argsort(np.abs(th[inner] - omega0), kind="stable")]
+        blk = list(inner[:m])
+        for j in order:
+            if len(blk) >= m:
+                break
+            if j not in blk:
+                blk.append(j)
+        blk = np.array(blk)
+        out = inner[:n_roots] if len(inner) >= n_roots else tgt
         info.update(cycles=cycle + 1, products=ops.count, basis=Q.shape[1])
-        sel = np.sort(tgt)
-        sel = sel[np.argsort(th[sel])]
+        sel = out[np.argsort(th[out])]
         result = (th[sel], Q @ Xs[:, sel], Q @ Ys[:, sel])
         info["residuals"] = rnorm[sel]
-        if np.all(rnorm[tgt] <= tol):
+        if np.all(rnorm[tgt] <= tol) and np.all(rnorm[inner] <= tol):
             info["converged"] = True
             break
         # corrections: diagonal of the shifted pencil in (u, w) coordinates

@@ -124,6 +124,8 @@ def lib() -> C.CDLL:
         L.ppint_gemm.restype = C.c_int
         L.ppint_gemm_group.argtypes = [i32, i32, C.POINTER(ppint_gemm_member), C.POINTER(i32)]
         L.ppint_gemm_group.restype = C.c_int
+        L.ppint_partial_syev.argtypes = [i32, vp, dbl, i32, vp, vp, C.POINTER(i32)]
+        L.ppint_partial_syev.restype = C.c_int
         L.ppint_syev.argtypes = [i32, vp, vp, vp]
         L.ppint_syev.restype = C.c_int
         L.ppint_cholesky.argtypes = [i32, vp, vp]
@@ -327,6 +329,13 @@ def gemm_group(members, fp32=False) -> int:
     g = C.c_int32()
     _check(lib().ppint_gemm_group(1 if fp32 else 0, len(members), arr, C.byref(g)))
     return g.value
+
+
+def partial_syev(A, target, p, lam, Z) -> int:
+    q = C.c_int32()
+    _check(lib().ppint_partial_syev(A.shape[0], A.data_ptr(), float(target), int(p), lam.data_ptr(), Z.data_ptr(),
+                                    C.byref(q)))
+    return q.value
 
 
 def syev(A, w, Z):

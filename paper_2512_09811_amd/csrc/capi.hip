@@ -302,6 +302,20 @@ pp_status ppint_gemm_group(int32_t fp32, int32_t n, const ppint_gemm_member* m, 
   });
 }
 
+pp_status ppint_partial_syev(int32_t n, const double* A, double target, int32_t p, double* lam, double* Z,
+                             int32_t* q) {
+  std::string err;
+  double* scr = nullptr;
+  pp_status st = guarded(&err, [&] {
+    PPW_HIP(hipMalloc(&scr, sizeof(double) * ppw::partial_syev_scratch(n, p)));
+    const int got = ppw::partial_syev(n, A, target, p, lam, Z, scr, nullptr);
+    PPW_HIP(hipDeviceSynchronize());
+    if (q) *q = got;
+  });
+  if (scr) (void)hipFree(scr);
+  return st;
+}
+
 pp_status ppint_syev(int32_t n, const double* A, double* w, double* Z) {
   std::string err;
   return guarded(&err, [&] {

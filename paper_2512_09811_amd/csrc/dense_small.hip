@@ -379,15 +379,18 @@ __device__ int sturm_count(int n, const double* d, const double* e, double x, do
   return c;
 }
 
-// Eigenvalues lo..lo+p-1 of the tridiagonal around 'target' by bisection (one per
-// thread) and their vectors by inverse iteration with partially pivoted LU.
-// V[t][n]: vector t; lam[t]; work: 6 n doubles per thread.
+// The p eigenvalues of the tridiagonal nearest 'target': the p below and the p above
+// it by bisection (one per thread), the p nearest of those, then their vectors by
+// inverse iteration with partially pivoted LU.  V[t][n]: vector t; lam[t] ascending;
+// work: 6 n doubles per thread.  p <= 64.
 __global__ __launch_bounds__(kT) void slice_kernel(int n, const double* __restrict__ d, const double* __restrict__ e,
                                                    double target, int p, double* __restrict__ lam,
                                                    double* __restrict__ V, double* __restrict__ work) {
   __shared__ double sd[kMaxN], se[kMaxN];
   __shared__ double bounds[3];
-  __shared__ int lo_s;
+  __shared__ int lo_s, nc_s;
+  __shared__ double cand[128];
+  __shared__ int pick[64];
   const int tid = threadIdx.x;
   for (int i = tid; i < n; i += kT) {
     sd[i] = d[i];
@@ -406,16 +409,18 @@ __global__ __launch_bounds__(kT) void slice_kernel(int n, const double* __restri
     bounds[0] = gl - 1e-14 * span;
     bounds[1] = gu + 1e-14 * span;
     bounds[2] = fmax(DBL_MIN, 1e-300 + 4.0 * DBL_MIN * fmax(1.0, emax));
+    // the p eigenvalues nearest the target lie among the p below and the p above it
     const int j0 = sturm_count(n, sd, se, target, bounds[2]);
-    int lo = j0 - p / 2;
-    lo = max(0, min(lo, n - p));
+    const int lo = max(0, j0 - p);
     lo_s = lo;
+    nc_s = min(n, j0 + p) - lo;
   }
   __syncthreads();
   const double pivmin = bounds[2];
   const double scale = fmax(fabs(bounds[0]), fabs(bounds[1]));
-  if (tid < p) {
-    const int idx = lo_s + tid;  // want the idx-th smallest (0-based)
+  // bisection for every candidate index (ascending eigenvalue order)
+  if (tid < nc_s) {
+    const int idx = lo_s + tid;  // the idx-th smallest (0-based)
     double a = bounds[0], b = bounds[1];
     for (int it = 0; it < 200 && (b - a) > 4.0 * DBL_EPSILON * fmax(fabs(a), fabs(b)) + DBL_MIN; ++it) {
       const double mid = 0.5 * (a + b);
@@ -424,7 +429,24 @@ __global__ __launch_bounds__(kT) void slice_kernel(int n, const double* __restri
       else
         a = mid;
     }
-    const double lmb = 0.5 * (a + b);
+    cand[tid] = 0.5 * (a + b);
+  }
+  __syncthreads();
+  // the p candidates nearest the target (ties: the lower), kept in ascending order;
+  // candidates are ascending, so the nearest p form a contiguous run
+  if (tid == 0) {
+    int i0 = 0, i1 = nc_s;  // shrink [i0, i1) from the farther end
+    while (i1 - i0 > p) {
+      if (fabs(cand[i1 - 1] - target) >= fabs(cand[i0] - target))
+        --i1;
+      else
+        ++i0;
+    }
+    for (int j = 0; j < p; ++j) pick[j] = i0 + j;
+  }
+  __syncthreads();
+  if (tid < p) {
+    const double lmb = cand[pick[tid]];
     lam[tid] = lmb;
     // inverse iteration on (T - lmb I)
     double* dl = work + (long)tid * 6 * n;

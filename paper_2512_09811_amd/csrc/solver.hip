@@ -972,7 +972,7 @@ void Solver::run(double* energies, double* vectors, double* osc, pp_solve_info* 
 
   int knew = m_;  // columns in the new block (X in V_[0..k), Y in V_[k..2k))
   Ritz R;
-  std::vector<int> tgt, blk;
+  std::vector<int> tgt, blk, inner, out;
   bool converged = false;
   int cycle = 0;
   const double clampv = opt_.d_clamp > 0 ? opt_.d_clamp : 1e-4;
@@ -1048,14 +1048,41 @@ void Solver::run(double* energies, double* vectors, double* osc, pp_solve_info* 
     std::vector<int> order(n);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return R.fold[a] < R.fold[b]; });
-    blk.assign(order.begin(), order.begin() + std::min(m_, n));
+    // targets: the n_roots pairs with the smallest folded quotient.  Every Ritz pair
+    // whose value lies within the farthest target's distance of omega0 ("inner") must
+    // converge too: an eigenvector already in the subspace can show up as a polluted
+    // Ritz pair (large residual, large folded quotient) next to omega0, and would
+    // otherwise be dropped at a restart while farther roots converge.  The inner pairs
+    // lead the block, so they get corrections and survive restarts.
     tgt.assign(order.begin(), order.begin() + std::min(nr_, n));
+    double dmax = 0.0;
+    for (int j : tgt) dmax = std::max(dmax, std::fabs(R.th[j] - w0_));
+    inner.clear();
+    for (int j = 0; j < n; ++j)
+      if (std::fabs(R.th[j] - w0_) <= dmax * (1.0 + 1e-12)) inner.push_back(j);
+    std::stable_sort(inner.begin(), inner.end(),
+                     [&](int a, int b) { return std::fabs(R.th[a] - w0_) < std::fabs(R.th[b] - w0_); });
+    blk.clear();
+    for (int j : inner)
+      if ((int)blk.size() < m_) blk.push_back(j);
+    for (int j : order) {
+      if ((int)blk.size() >= std::min(m_, n)) break;
+      if (std::find(blk.begin(), blk.end(), j) == blk.end()) blk.push_back(j);
+    }
     bool all = (int)tgt.size() == nr_;
     double worst = 0.0;
     for (int j : tgt) {
       all = all && R.rn[j] <= opt_.tol;
       worst = std::max(worst, R.rn[j]);
     }
+    for (int j : inner) {
+      all = all && R.rn[j] <= opt_.tol;
+      worst = std::max(worst, R.rn[j]);
+    }
+    // the window's result: the n_roots inner pairs nearest omega0 (the targets while
+    // some inner pair is unresolved)
+    if ((int)inner.size() >= nr_) out.assign(inner.begin(), inner.begin() + nr_);
+    else out = tgt;
     if (worst < 0.5 * best_worst) {
       best_worst = worst;
       since_best = 0;
@@ -1079,15 +1106,15 @@ void Solver::run(double* energies, double* vectors, double* osc, pp_solve_info* 
         continue;
       }
       if (refined && all) {
-        auto rex = exact_residuals(tgt, R.th);
+        auto rex = exact_residuals(out, R.th);
         if (trace_) {
           double mx = 0.0;
           for (double x : rex) mx = std::max(mx, x);
           std::fprintf(stderr, "[ppwin] window %d FP64 residual check: worst %.3e\n", id_, mx);
         }
         bool ok = true;
-        for (size_t q = 0; q < tgt.size(); ++q) {
-          R.rn[tgt[q]] = rex[q];
+        for (size_t q = 0; q < out.size(); ++q) {
+          R.rn[out[q]] = rex[q];
           ok = ok && rex[q] <= opt_.tol;
         }
         if (ok) {
@@ -1124,8 +1151,8 @@ void Solver::run(double* energies, double* vectors, double* osc, pp_solve_info* 
                                                         V_ + (size_t)knew * N_);
     if (nb_ + 2 * opt_.krylov_steps * knew > nbmax_) restart(blk);
   }
-  // outputs for the targets, ascending energy
-  std::vector<int> sel = tgt;
+  // outputs: the window's roots, ascending energy
+  std::vector<int> sel = out;
   std::sort(sel.begin(), sel.end(), [&](int a, int b) { return R.th[a] < R.th[b]; });
   const int r = (int)sel.size();
   for (int q = 0; q < r; ++q) energies[q] = R.th[sel[q]];

@@ -5,7 +5,9 @@ the seeded synthetic systems; no value comes from the HIP path.  Usage:
     python tests/golden/make_golden.py [workload ...]
 Each workload produces tests/golden/<workload>.json with, per window, the
 oracle's roots nearest omega0 (Ha, ascending) and their dipole oscillator
-strengths.
+strengths.  Second-order workloads also get a "survey": 24 windows from 0.35 to
+1.5 Ha (10 roots each, energies only) that exercise the completeness of the
+window solver across the spectrum.
 """
 import json
 import os
@@ -36,6 +38,11 @@ def make(name):
         f = pencil.oscillator_strengths(om[idx], X[:, idx], Y[:, idx], sys_.dip)
         out["windows"].append(dict(omega0=float(w0), n_roots=int(nr), energies=[float(x) for x in om[idx]],
                                    osc=[float(x) for x in f]))
+    if cfg["order"] >= 2:
+        out["survey"] = []
+        for w0 in np.linspace(0.35, 1.5, 24):
+            idx = pencil.select_window(om, float(w0), 10)
+            out["survey"].append(dict(omega0=float(w0), n_roots=10, energies=[float(x) for x in np.sort(om[idx])]))
     out["oracle_seconds"] = time.time() - t0
     path = os.path.join(HERE, f"{name}.json")
     with open(path, "w") as fh:

@@ -135,3 +135,45 @@ def test_gemm_group(B, fp32):
         got = m["C"].double().cpu().numpy()
         tol = (2e-6 if fp32 else 1e-13) * np.sqrt(K) * 3
         np.testing.assert_allclose(got, ref, rtol=0, atol=tol)
+
+
+def _spectrum_matrix(lam, seed):
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((len(lam), len(lam))))
+    return (Q * lam) @ Q.T
+
+
+@pytest.mark.parametrize("case", ["uniform", "dense_near_target", "near_degenerate", "edge_target", "small"])
+def test_partial_syev(B, case):
+    """The p eigenpairs nearest a target (projected problem of the window solver)."""
+    rng = np.random.default_rng(5)
+    n, p, target = 400, 34, 0.9025
+    if case == "uniform":
+        lam = rng.uniform(0.1, 3.0, n)
+    elif case == "dense_near_target":
+        lam = np.concatenate([target + 5e-4 * np.arange(-60, 60) + 1e-5 * rng.standard_normal(120),
+                              rng.uniform(0.14, 9.0, n - 120)])
+    elif case == "near_degenerate":
+        base = target + 4e-4 * np.arange(-20, 20)
+        lam = np.concatenate([base, base[::3] + 1e-5, base[1::5] + 1e-8, base[2::7] + 1e-12,
+                              rng.uniform(0.14, 9.0, n - 40 - len(base[::3]) - len(base[1::5]) - len(base[2::7]))])
+    elif case == "edge_target":
+        target = 0.05
+        lam = rng.uniform(0.1, 3.0, n)
+    else:
+        n, p = 30, 12
+        lam = rng.uniform(0.5, 1.5, n)
+    A = _spectrum_matrix(lam, 11)
+    dA = torch.tensor(A, device="cuda")
+    lam_d = torch.zeros(p, dtype=torch.float64, device="cuda")
+    Z = torch.zeros(n * p, dtype=torch.float64, device="cuda")
+    q = B.partial_syev(dA, target, p, lam_d, Z)
+    w = lam_d.cpu().numpy()[:q]
+    Zh = Z.cpu().numpy().reshape(n, p)[:, :q]
+    exact = np.sort(lam)
+    nearest = np.sort(exact[np.argsort(np.abs(exact - target), kind="stable")[:p]])
+    assert q == p, (q, p)
+    np.testing.assert_allclose(np.sort(w), nearest, rtol=0, atol=1e-12 * np.abs(lam).max())
+    res = np.linalg.norm(A @ Zh - Zh * w, axis=0)
+    assert res.max() < 1e-10 * np.abs(lam).max(), res.max()
+    np.testing.assert_allclose(Zh.T @ Zh, np.eye(q), atol=1e-10)

@@ -179,3 +179,28 @@ def test_window_mixed_precision(P, omega0, nr):
         e, vec, f, info = h.window_solve(omega0, nr)
     _check_window(sys, 2, omega0, nr, e, vec, f, info)
     assert np.all(info["residual"] <= 1e-9)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_window_survey_completeness(P, precision):
+    """The full 40/160/600 workload in the launch configuration the benchmark times
+    (amplitudes stored, windows batched): 24 windows across the spectrum, each must
+    return exactly the oracle's 10 roots nearest omega0 (no root missed, none
+    substituted), to 1e-8 Ha.  Mixed precision runs every third window."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "mp2_o40_v160_x600.json")))
+    survey = g["survey"] if precision == "fp64" else g["survey"][::3]
+    from synth.gen import gen_config
+    sys = gen_config("mp2_o40_v160_x600")
+    prec = P.PP_FP64 if precision == "fp64" else P.PP_FP32
+    print(f"[survey] {len(survey)} windows, {precision}", flush=True)
+    with P.Handle.from_system(sys, order=2, store_amplitudes=1, precision=prec) as h:
+        for b0 in range(0, len(survey), 8):
+            part = survey[b0:b0 + 8]
+            e, _, _, infos = h.window_solve_batch([w["omega0"] for w in part], 10, vectors=False, osc=False)
+            for k, w in enumerate(part):
+                np.testing.assert_allclose(e[k], w["energies"], rtol=0, atol=1e-8,
+                                           err_msg=f"window {w['omega0']:.4f}")
+                assert np.all(infos[k]["converged"] == 1)
+            print(f"[survey] windows {b0}..{b0 + len(part) - 1} ok", flush=True)
