@@ -1,0 +1,107 @@
+"""Products at the full 200/800/3000 and 256/1024/4096 sizes (amplitudes rebuilt in
+strips, never stored), through the C ABI.
+
+No dense oracle exists at these sizes (particle-hole dimension 1.6e5 and 2.6e5),
+so the checks are:
+  * first order: sampled rows of A V and B V against the row oracle
+    (oracle.columns, exact definitions), to 1e-12 of the row scale;
+  * second order, complete A, B, S: the projected matrices U^T (A U), U^T (B U),
+    U^T (S U) on a random block U are symmetric to rounding (A, B, S are
+    symmetric; a transposed operand or a mis-indexed term in any second-order
+    contraction breaks this), the second-order part is present and small next to
+    the first-order one, and the metric's diagonal block is below the identity
+    (occupation numbers of the MP2 state);
+  * FP32 contractions agree with the FP64 path to single precision (smaller size).
+Inputs come from the seeded device generator (same recipe as the numpy one).
+"""
+import time
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+CASES = {"mp2_o200_v800_x3000": (3, 200, 800, 3000), "mp2_o256_v1024_x4096": (5, 256, 1024, 4096)}
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2512_09811_amd as P
+    P.lib()
+    return P
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fullsize_products(P, name):
+    from synth.device_gen import gen_device
+    from oracle import columns
+    seed, o, v, X = CASES[name]
+    N = o * v
+    t0 = time.time()
+    t = gen_device(seed, o, v, X)
+    torch.cuda.synchronize()
+    print(f"[fullsize] {name}: inputs drawn in {time.time() - t0:.1f} s", flush=True)
+    k = 3
+    rng = np.random.default_rng(seed + 100)
+    U = torch.tensor(rng.standard_normal((k, N)), device="cuda")
+    out = {key: torch.empty_like(U) for key in ("A1", "B1", "S1", "A2", "B2", "S2")}
+    t0 = time.time()
+    with P.Handle(t["eps"], t["B_oo"], t["B_ov"], t["B_vv"], t["dip"], order=2, device_ptrs=True,
+                  store_amplitudes=0) as h:
+        torch.cuda.synchronize()
+        print(f"[fullsize] setup {time.time() - t0:.1f} s, device bytes {h.device_bytes() / 2**30:.1f} GiB, "
+              f"E_MP2 {h.mp2_energy():.6f}", flush=True)
+        t0 = time.time()
+        h.products(U, out["A1"], out["B1"], out["S1"], order=1)
+        h.products(U, out["A2"], out["B2"], out["S2"], order=2)
+        torch.cuda.synchronize()
+        print(f"[fullsize] products {time.time() - t0:.1f} s", flush=True)
+        e2 = h.mp2_energy()
+    assert e2 < 0.0
+    Uh = U.cpu().numpy()
+    r = {key: val.cpu().numpy() for key, val in out.items()}
+    # first order: sampled rows against the row oracle
+    rows = sorted(int(x) for x in rng.choice(N, 10, replace=False))
+    eps = t["eps"].cpu().numpy()
+    B_ov = t["B_ov"].cpu().numpy()
+    Boo_i = [t["B_oo"][:, ia // v, :].cpu().numpy() for ia in rows]
+    Bvv_a = [t["B_vv"][:, ia % v, :].cpu().numpy() for ia in rows]
+    AV, BV = columns.first_order_rows(eps, o, v, B_ov, rows, Boo_i, Bvv_a, Uh)
+    scale = np.abs(AV).max()
+    np.testing.assert_allclose(r["A1"][:, rows], AV, rtol=0, atol=1e-12 * scale)
+    np.testing.assert_allclose(r["B1"][:, rows], BV, rtol=0, atol=1e-12 * np.abs(BV).max())
+    np.testing.assert_allclose(r["S1"], Uh, rtol=0, atol=0)
+    # second order: symmetric projections, a present and small correction
+    for key in ("A2", "B2", "S2"):
+        G = Uh @ r[key].T
+        asym = np.abs(G - G.T).max()
+        assert asym <= 1e-12 * np.abs(G).max(), (key, asym, np.abs(G).max())
+    dA = np.linalg.norm(r["A2"] - r["A1"]) / np.linalg.norm(r["A1"])
+    dB = np.linalg.norm(r["B2"] - r["B1"]) / np.linalg.norm(r["B1"])
+    assert 1e-7 < dA < 0.1 and 1e-7 < dB < 0.5, (dA, dB)
+    # S = 1 - (occupied and virtual MP2 densities): u^T S u < u^T u for every u
+    q = np.einsum("kn,kn->k", Uh, r["S2"]) / np.einsum("kn,kn->k", Uh, Uh)
+    assert np.all(q < 1.0) and np.all(q > 0.8), q
+
+
+def test_fullsize_fp32_products(P):
+    """FP32 contractions (FP64 diagonal and assembly) against the FP64 path, amplitudes
+    rebuilt in strips, at a size with several strips and GEMM tiles."""
+    from synth.device_gen import gen_device
+    o, v, X = 64, 256, 768
+    t = gen_device(17, o, v, X)
+    N = o * v
+    rng = np.random.default_rng(3)
+    U = torch.tensor(rng.standard_normal((4, N)), device="cuda")
+    o64 = [torch.empty_like(U) for _ in range(3)]
+    o32 = [torch.empty_like(U) for _ in range(3)]
+    with P.Handle(t["eps"], t["B_oo"], t["B_ov"], t["B_vv"], t["dip"], order=2, device_ptrs=True,
+                  store_amplitudes=0, strip_rows=5, precision=P.PP_FP32) as h:
+        h.products(U, *o64, order=2, fp32=False)
+        h.products(U, *o32, order=2, fp32=True)
+    for j in range(3):
+        a, b = o64[j].cpu().numpy(), o32[j].cpu().numpy()
+        err = np.abs(a - b).max()
+        assert err <= 2e-6 * np.abs(a).max(), (j, err, np.abs(a).max())

@@ -270,3 +270,19 @@ def test_p9_variance_vanishes_for_converged_vectors():
     # a perturbed vector has a strictly positive variance
     x = U[:, 3] + 1e-2 * U[:, 7]
     assert pencil.variance(A, x) > 1e-8
+
+
+def test_first_order_rows_match_dense_assembly():
+    """The sampled-row oracle used at full sizes agrees with the dense first-order
+    assembly (a second, independent route through the same definitions)."""
+    from oracle import columns
+    sys_ = gen(3, 5, 13, 29)
+    A, B, S = dense.assemble(sys_, 1)
+    rng = np.random.default_rng(0)
+    V = rng.standard_normal((3, sys_.N))
+    rows = [0, 7, 20, 64]
+    Boo_i = [sys_.B_oo[:, r // sys_.v, :] for r in rows]
+    Bvv_a = [sys_.B_vv[:, r % sys_.v, :] for r in rows]
+    AV, BV = columns.first_order_rows(sys_.eps, sys_.o, sys_.v, sys_.B_ov, rows, Boo_i, Bvv_a, V)
+    np.testing.assert_allclose(AV, (V @ A.T)[:, rows], rtol=0, atol=1e-14)
+    np.testing.assert_allclose(BV, (V @ B.T)[:, rows], rtol=0, atol=1e-14)
