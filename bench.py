@@ -76,6 +76,8 @@ def parse():
                     help="serving stream instead of the batched-window workload (its own JSON line)")
     ap.add_argument("--requests", type=int, default=48, help="serving: timed requests")
     ap.add_argument("--occ", default="16,40", help="serving: n_occ range lo,hi (the full stream is 16,128)")
+    ap.add_argument("--no-plain-compare", action="store_true",
+                    help="serving: skip solving the timed requests one by one on plain FP64 handles")
     return ap.parse_args()
 
 
@@ -160,6 +162,26 @@ def serve_main(args):
     st = srv.stats()
     srv.close()
     conv = sum(1 for r in res if r["status"] == P.PP_OK and np.all(r["converged"] == 1))
+    # the same requests again: all at once into a fresh server (saturated), then one FP64
+    # handle per request, one at a time (the plain path)
+    seq = sat_same = None
+    if not args.no_plain_compare:
+        t1 = time.perf_counter()
+        with P.Server(precision=prec) as srv2:
+            ids2 = [srv2.submit_system(s_, w, nr) for s_, w, nr in timed]
+            for i in ids2:
+                srv2.wait(i, allow_unconverged=True)
+            st2 = srv2.stats()
+        sat_same = len(timed) / (time.perf_counter() - t1)
+        print(f"[serve] saturated on the timed requests: {sat_same:.2f} solves/s, "
+              f"{st2['mean_requests_per_pass']:.2f} requests per pass", file=sys.stderr, flush=True)
+        t1 = time.perf_counter()
+        for j, (s_, w, nr) in enumerate(timed):
+            with P.Handle.from_system(s_, order=2) as h:
+                h.window_solve(w, nr, allow_unconverged=True)
+            if (j + 1) % 8 == 0:
+                print(f"[serve] plain path {j + 1}/{len(timed)}", file=sys.stderr, flush=True)
+        seq = len(timed) / (time.perf_counter() - t1)
     lat = np.array([r["latency_seconds"] for r in res])
     occ = [s_.o for s_, _, _ in timed]
     line = {
@@ -189,6 +211,9 @@ def serve_main(args):
         "peak_running": st["peak_running"],
         "sigma_tflops": st["product_flops"] / st["product_seconds"] / 1e12 if st["product_seconds"] > 0 else 0.0,
         "sigma_fraction_of_time": st["product_seconds"] / elapsed,
+        "saturated_solves_per_s_same_requests": sat_same,
+        "plain_fp64_one_at_a_time_solves_per_s": seq,
+        "saturated_over_plain": (sat_same / seq) if seq else None,
     }
     print(json.dumps(line), flush=True)
 

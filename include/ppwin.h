@@ -84,10 +84,10 @@ typedef struct {
                                product; -1 (default): keep them when they fit the budget */
   int32_t strip_rows;       /* occupied rows per amplitude strip (0 = chosen from the budget) */
   double tol;               /* residual tolerance |(M - theta Sigma) y| / |y| (default 1e-9) */
-  int32_t block;            /* block size (0: n_roots + max(2, n_roots/2)) */
+  int32_t block;            /* block size (0: n_roots + 2) */
   int32_t krylov_steps;     /* basis vectors per cycle: corrections + (krylov_steps-1)
                                weighted-Jacobi steps (default 2) */
-  int32_t max_basis;        /* largest subspace (default 400, at most 512) */
+  int32_t max_basis;        /* largest subspace (default 480, at most 512) */
   int32_t max_cycles;       /* default 200 */
   double d_clamp;           /* smallest |diagonal| of the Jacobi splitting (default 1e-4 Ha) */
   uint64_t hbm_budget;      /* bytes the handle may allocate (0: 90% of free device memory) */

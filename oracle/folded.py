@@ -142,8 +142,8 @@ def folded_window_solve(A, B, S, omega0, n_roots, *, block=None, krylov_steps=2,
     linear combination of the stored (A+B)Q, (A-B)Q and SQ.
     """
     N = A.shape[0]
-    m = min(block or (n_roots + max(2, n_roots // 2)), N)
-    nb_max = min(max_basis or max(400, 20 * m), N)
+    m = min(block or (n_roots + 2), N)
+    nb_max = min(max_basis or max(480, 20 * m), N)
     ops = _Ops(A, B, S)
     dA, dB, dS = np.diag(A).copy(), np.diag(B).copy(), np.diag(S).copy()
 

@@ -36,7 +36,7 @@ void pp_default_options(pp_options* opt) {
   opt->tol = 1e-9;
   opt->block = 0;
   opt->krylov_steps = 2;
-  opt->max_basis = 400;
+  opt->max_basis = 480;
   opt->max_cycles = 200;
   opt->d_clamp = 1e-4;
   opt->hbm_budget = 0;

@@ -13,7 +13,7 @@ struct SolveOptions {
   double tol = 1e-9;
   int block = 0;
   int krylov_steps = 2;
-  int max_basis = 400;
+  int max_basis = 480;
   int max_cycles = 200;
   double d_clamp = 1e-4;
   unsigned long long seed = 0;

@@ -501,9 +501,9 @@ struct SolverDims {
 };
 SolverDims solver_dims(long N, int nroots, const SolveOptions& o) {
   SolverDims d;
-  d.m = o.block > 0 ? o.block : nroots + std::max(2, nroots / 2);
+  d.m = o.block > 0 ? o.block : nroots + 2;
   d.m = (int)std::min<long>(d.m, N);
-  d.nbmax = (int)std::min<long>(o.max_basis > 0 ? o.max_basis : 400, N);
+  d.nbmax = (int)std::min<long>(o.max_basis > 0 ? o.max_basis : 480, N);
   d.nbmax = std::max(d.nbmax, std::min<int>((int)N, 2 * d.m));
   d.kmax = 2 * d.m;
   return d;
@@ -803,6 +803,21 @@ class Solver {
     coeff_dots_kernel<<<(k + 63) / 64, 64, 0, s_>>>(nb_, k, kmax_, X1, Y1, X2, Y2, out);
   }
 
+  // FP64 products of the whole current basis (mixed precision: the subspace built with
+  // FP32 products is kept, only its products are recomputed exactly)
+  void remultiply_basis() {
+    for (int c0 = 0; c0 < nb_; c0 += kmax_) {
+      const int kc = std::min(kmax_, nb_ - c0);
+      const size_t off = (size_t)c0 * N_;
+      products(kc, Q_ + off, true);
+      axpby((long)kc * N_, 1.0, AV_, 0.0, P0_ + off, s_);
+      axpby((long)kc * N_, 1.0, BV_, 1.0, P0_ + off, s_);
+      axpby((long)kc * N_, 1.0, AV_, 0.0, P1_ + off, s_);
+      axpby((long)kc * N_, -1.0, BV_, 1.0, P1_ + off, s_);
+      PPW_HIP(hipMemcpyAsync(PS_ + off, SV_, sizeof(double) * kc * N_, hipMemcpyDeviceToDevice, s_));
+    }
+  }
+
   // thick restart: new basis = orthonormal span of the X+Y and X-Y halves of the block's Ritz vectors
   void restart(const std::vector<int>& blk) {
     const int n = nb_;
@@ -1094,11 +1109,13 @@ void Solver::run(double* energies, double* vectors, double* osc, pp_solve_info* 
       std::fprintf(stderr, "[ppwin] window %d omega0 %.4f cycle %d basis %d products %ld worst %.3e refined %d\n", id_,
                    w0_, cycle, nb_, products_, worst, refined ? 1 : 0);
     if (mixed) {
-      // FP32 products build the subspace; restart blocks get FP64 products; the
-      // returned vectors are accepted on FP64 residuals only.
+      // FP32 products build the subspace until the window is resolved to the FP32
+      // level (or stops improving); then the basis gets FP64 products once and the
+      // solve continues as in FP64 (every later product FP64, restart blocks FP64);
+      // the returned vectors are accepted on residuals of FP64 products only.
       if (!refined && (all || worst <= switch_tol || stalled)) {
         refined_ = true;
-        restart(blk);
+        remultiply_basis();
         refined = true;
         knew = 0;
         best_worst = 1e300;
@@ -1122,13 +1139,6 @@ void Solver::run(double* energies, double* vectors, double* osc, pp_solve_info* 
           ++cycle;
           break;
         }
-        restart(blk);
-        knew = 0;
-        best_worst = 1e300;
-        since_best = 0;
-        continue;
-      }
-      if (refined && stalled) {
         restart(blk);
         knew = 0;
         best_worst = 1e300;

