@@ -138,7 +138,9 @@ pp_status pp_window_solve(pp_handle* h, double omega0, int32_t n_roots, double* 
 /* Several windows of the same system in one call: the windows are solved
  * concurrently (one host thread and one HIP stream each for the subspace work) and
  * their products are merged into shared product passes, so one pass of the
- * amplitude contraction serves every window.  omega0[n_windows]; outputs are
+ * amplitude contraction serves several windows (two fixed groups of windows
+ * alternate passes, so one group's subspace work overlaps the other's products;
+ * results are reproducible).  omega0[n_windows]; outputs are
  * window-major: energies[n_windows][n_roots], vectors[n_windows][n_roots][2][n_occ][n_vir]
  * (nullable), osc[n_windows][n_roots] (nullable), info[n_windows] (nullable; the
  * product time/flops fields hold the totals of the whole call).  Each window's

@@ -57,7 +57,8 @@ void window_solve(Context& c, const SolveOptions& opt, double omega0, int n_root
                   double* vectors, double* osc, pp_solve_info* info);
 
 // Several windows of one system solved concurrently (one host thread and stream
-// each); their products are merged into shared product passes.  Outputs are laid
+// each); their products are merged into shared product passes (two fixed groups of
+// windows alternate passes).  Outputs are laid
 // out window-major: energies[w][n_roots], vectors[w][n_roots][2][N], osc[w][n_roots],
 // info[w].  Throws the first non-convergence after writing every output.
 void window_solve_many(Context& c, const SolveOptions& opt, int nw, const double* omega0, int n_roots,

@@ -402,12 +402,15 @@ GemmDesc gd(int M, int N, int K, int tA, long lda, int tB, long ldb, long ldc) {
 // with a completion event per request.  Requests are served in window order, so the
 // batch composition (and therefore every rounding) is a deterministic function of
 // the inputs.
-// Merges the product requests of the windows of one system into shared passes: a
-// pass runs when every window still solving has a request pending.
+// Merges the product requests of a group of windows of one system into shared
+// passes: a pass runs when every window of the group still solving has a request
+// pending.  Several groups may share a context: 'enqueue' serializes their passes
+// on the context's stream (and its product workspace).
 class ProductBatcher : public ProductSink {
  public:
   using Req = ProductRequest;
-  ProductBatcher(Context& c, int active, int precision) : c_(c), active_(active), prec_(precision) {}
+  ProductBatcher(Context& c, int active, int precision, std::mutex* enqueue)
+      : c_(c), active_(active), prec_(precision), enqueue_(enqueue) {}
   ~ProductBatcher() override {
     for (void* q : bufs_) c_.arena.free(q);
   }
@@ -442,6 +445,7 @@ class ProductBatcher : public ProductSink {
   void serve() {
     std::exception_ptr err;
     std::sort(pending_.begin(), pending_.end(), [](const Req* a, const Req* b) { return a->id < b->id; });
+    std::unique_lock<std::mutex> eq(*enqueue_);
     try {
       hipStream_t s = c_.stream;
       const long N = c_.N;
@@ -486,6 +490,7 @@ class ProductBatcher : public ProductSink {
   Context& c_;
   int active_;
   int prec_;
+  std::mutex* enqueue_;
   std::mutex mu_;
   std::condition_variable cv_;
   std::vector<Req*> pending_;
@@ -1211,14 +1216,25 @@ void window_solve_many(Context& c, const SolveOptions& opt, int nw, const double
   if (nw < 1) return;
   c.resolve_stats();
   const double sig0 = c.stats.seconds, flop0 = c.stats.flops;
-  ProductBatcher pb(c, nw, opt.precision);
-  std::vector<std::unique_ptr<Solver>> sv;
-  int ktot = 0;
-  for (int w = 0; w < nw; ++w) {
-    sv.emplace_back(new Solver(c, opt, omega0[w], n_roots, &pb, w));
-    ktot += sv.back()->kmax();
+  // Two groups of windows (even and odd index) with passes of their own: while one
+  // group's pass runs, the other group's windows solve their projected problems, so
+  // the product stream does not wait for every window's subspace work.  Group
+  // membership is fixed, so every pass (and every result) is reproducible.
+  const int ngroups = nw >= 2 ? 2 : 1;
+  std::mutex enqueue;
+  std::vector<std::unique_ptr<ProductBatcher>> pbs;
+  for (int g = 0; g < ngroups; ++g) {
+    int members = 0;
+    for (int w = g; w < nw; w += ngroups) ++members;
+    pbs.emplace_back(new ProductBatcher(c, members, opt.precision, &enqueue));
   }
-  pb.reserve(ktot);
+  std::vector<std::unique_ptr<Solver>> sv;
+  std::vector<int> ktot(ngroups, 0);
+  for (int w = 0; w < nw; ++w) {
+    sv.emplace_back(new Solver(c, opt, omega0[w], n_roots, pbs[w % ngroups].get(), w));
+    ktot[w % ngroups] += sv.back()->kmax();
+  }
+  for (int g = 0; g < ngroups; ++g) pbs[g]->reserve(ktot[g]);
   PPW_HIP(hipStreamSynchronize(c.stream));
   std::vector<std::exception_ptr> errs(nw);
   auto work = [&](int w) {
@@ -1230,7 +1246,7 @@ void window_solve_many(Context& c, const SolveOptions& opt, int nw, const double
     } catch (...) {
       errs[w] = std::current_exception();
     }
-    pb.leave();
+    pbs[w % ngroups]->leave();
   };
   if (nw == 1) {
     work(0);
