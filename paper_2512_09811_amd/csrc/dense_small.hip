@@ -10,6 +10,7 @@
 // Wilkinson-type shifts (the textbook tred2/tql2 pair), with the scalar
 // recurrence run by one thread and each rotation sequence applied to all rows of
 // the eigenvector matrix in parallel.  Eigenvalues are returned ascending.
+#include <algorithm>
 #include <cfloat>
 #include <vector>
 
@@ -278,6 +279,57 @@ __global__ __launch_bounds__(kT) void cholesky_kernel(int n, const double* __res
     __syncthreads();
   }
   if (tid == 0 && info) *info = bad;
+}
+
+// Panel of the blocked Cholesky (one workgroup): columns j0..j0+jb-1 of the lower
+// factor, in place in W (row-major n x n; only the lower triangle is read); the
+// update of the trailing columns is a GEMM issued by the host.  info (nullable):
+// 0 on success, j+1 for the first non-positive pivot j (later panels then stop).
+__global__ __launch_bounds__(256) void chol_panel_kernel(int n, int j0, int jb, double* __restrict__ W,
+                                                         int* __restrict__ info) {
+  __shared__ double piv;
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    if (info && j0 == 0) *info = 0;
+    bad = (info && *info != 0) ? 1 : 0;
+  }
+  __syncthreads();
+  if (bad) return;
+  const int kend = j0 + jb;
+  for (int j = j0; j < kend; ++j) {
+    if (tid == 0) {
+      const double d = W[(long)j * n + j];
+      if (d > 0.0) {
+        piv = sqrt(d);
+        W[(long)j * n + j] = piv;
+      } else {
+        bad = 1;
+        if (info) *info = j + 1;
+      }
+    }
+    __syncthreads();
+    if (bad) return;
+    const double l = piv;
+    for (int i = j + 1 + tid; i < n; i += blockDim.x) W[(long)i * n + j] /= l;
+    __syncthreads();
+    // rest of the panel: W[i][k] -= W[i][j] W[k][j] for j < k < kend, k <= i
+    const int nk = kend - (j + 1);
+    if (nk > 0) {
+      const long cnt = (long)(n - (j + 1)) * nk;
+      for (long idx = tid; idx < cnt; idx += blockDim.x) {
+        const int i = j + 1 + (int)(idx / nk), k = j + 1 + (int)(idx % nk);
+        if (k <= i) W[(long)i * n + k] -= W[(long)i * n + j] * W[(long)k * n + j];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void zero_upper_kernel(int n, double* __restrict__ L) {
+  const long nn = (long)n * n;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < nn; idx += (long)gridDim.x * blockDim.x)
+    if (idx % n > idx / n) L[idx] = 0.0;
 }
 
 __global__ __launch_bounds__(kT) void trinv_kernel(int n, const double* __restrict__ L, double* __restrict__ X) {
@@ -671,7 +723,36 @@ void small_trsm_lt(int n, const double* L, int p, double* B, hipStream_t s) {
 
 void small_cholesky(int n, const double* A, double* L, int* info, hipStream_t s) {
   if (n < 1 || n > kMaxN) throw InvalidArg("small_cholesky: n out of range");
-  cholesky_kernel<<<1, kT, 0, s>>>(n, A, L, info);
+  if (n <= 64) {
+    cholesky_kernel<<<1, kT, 0, s>>>(n, A, L, info);
+    PPW_LAUNCH_CHECK();
+    return;
+  }
+  // blocked right-looking: panels of 64 columns in one workgroup, trailing updates as
+  // GEMMs over the whole device (the unblocked sweep reads and writes the trailing
+  // matrix once per column through one CU)
+  constexpr int NB = 64;
+  PPW_HIP(hipMemcpyAsync(L, A, sizeof(double) * n * n, hipMemcpyDeviceToDevice, s));
+  for (int j0 = 0; j0 < n; j0 += NB) {
+    const int jb = std::min(NB, n - j0);
+    chol_panel_kernel<<<1, 256, 0, s>>>(n, j0, jb, L, info);
+    PPW_LAUNCH_CHECK();
+    const int j1 = j0 + jb, m2 = n - j1;
+    if (m2 > 0) {
+      GemmDesc d;
+      d.M = m2;
+      d.N = m2;
+      d.K = jb;
+      d.transA = 0;
+      d.lda = n;
+      d.transB = 1;
+      d.ldb = n;
+      d.ldc = n;
+      const double* panel = L + (size_t)j1 * n + j0;
+      gemm_f64(d, -1.0, panel, panel, 1.0, L + (size_t)j1 * n + j1, s);
+    }
+  }
+  zero_upper_kernel<<<(n * n + 255) / 256, 256, 0, s>>>(n, L);
   PPW_LAUNCH_CHECK();
 }
 

@@ -96,7 +96,7 @@ def test_small_syev(B, n):
     assert np.abs(Z.T @ Z - np.eye(n)).max() < 1e-12
 
 
-@pytest.mark.parametrize("n", [1, 4, 33, 257])
+@pytest.mark.parametrize("n", [1, 4, 33, 64, 65, 130, 257, 480, 512])
 def test_small_cholesky(B, n):
     rng = np.random.default_rng(n + 100)
     X = rng.standard_normal((n, n))
