@@ -39,7 +39,10 @@ __device__ double block_reduce_sum(double v, double* red) {
 }
 
 // W: n x n working copy (row-major, symmetric), Zc: n x n, column-major eigenvectors.
-__global__ __launch_bounds__(kT) void syev_kernel(int n, const double* __restrict__ A, double* __restrict__ w,
+// NT threads (1024 for the large projected problems; one wave for n <= 64, where the
+// block-wide barriers of the rotation sweeps cost more than the arithmetic).
+template <int NT>
+__global__ __launch_bounds__(NT) void syev_kernel(int n, const double* __restrict__ A, double* __restrict__ w,
                                                   double* __restrict__ Z, double* __restrict__ W,
                                                   double* __restrict__ Zr) {
   __shared__ double u[kMaxN];
@@ -52,14 +55,14 @@ __global__ __launch_bounds__(kT) void syev_kernel(int n, const double* __restric
   __shared__ int ctl[4];
   const int tid = threadIdx.x;
   const long nn = (long)n * n;
-  for (long i = tid; i < nn; i += kT) W[i] = A[i];
+  for (long i = tid; i < nn; i += NT) W[i] = A[i];
   __syncthreads();
 
   // ---- Householder tridiagonalization (W <- H W H, u_k stored in column k) ----
   for (int k = 0; k + 2 < n; ++k) {
     const int m = n - k - 1;  // length of the reflected part (rows k+1..n-1)
     double part = 0.0;
-    for (int r = tid; r < m; r += kT) {
+    for (int r = tid; r < m; r += NT) {
       const double x = W[(long)(k + 1 + r) * n + k];
       part += x * x;
     }
@@ -71,37 +74,37 @@ __global__ __launch_bounds__(kT) void syev_kernel(int n, const double* __restric
         d[k] = W[(long)k * n + k];
         e[k] = 0.0;
       }
-      for (int r = tid; r < m; r += kT) u[r] = 0.0;
+      for (int r = tid; r < m; r += NT) u[r] = 0.0;
       __syncthreads();
-      for (int r = tid; r < m; r += kT) W[(long)(k + 1 + r) * n + k] = 0.0;
+      for (int r = tid; r < m; r += NT) W[(long)(k + 1 + r) * n + k] = 0.0;
       __syncthreads();
       continue;
     }
     const double alpha = x0 > 0 ? -xnorm : xnorm;
     // v = x - alpha e1, |v|^2 = 2 xnorm^2 - 2 x0 alpha
     const double vnorm = sqrt(2.0 * xx - 2.0 * x0 * alpha);
-    for (int r = tid; r < m; r += kT) {
+    for (int r = tid; r < m; r += NT) {
       const double x = W[(long)(k + 1 + r) * n + k];
       u[r] = (r == 0 ? x - alpha : x) / vnorm;
     }
     __syncthreads();
     // p = A22 u (column form, symmetric)
-    for (int r = tid; r < m; r += kT) q[r] = 0.0;
+    for (int r = tid; r < m; r += NT) q[r] = 0.0;
     __syncthreads();
-    for (int r = tid; r < m; r += kT) {
+    for (int r = tid; r < m; r += NT) {
       double acc = 0.0;
       for (int cc = 0; cc < m; ++cc) acc += W[(long)(k + 1 + cc) * n + (k + 1 + r)] * u[cc];
       q[r] = acc;
     }
     __syncthreads();
     double kp = 0.0;
-    for (int r = tid; r < m; r += kT) kp += u[r] * q[r];
+    for (int r = tid; r < m; r += NT) kp += u[r] * q[r];
     const double K = block_reduce_sum(kp, red);
-    for (int r = tid; r < m; r += kT) q[r] = q[r] - K * u[r];
+    for (int r = tid; r < m; r += NT) q[r] = q[r] - K * u[r];
     __syncthreads();
     // A22 <- A22 - 2 (u q^T + q u^T)
     const long mm = (long)m * m;
-    for (long idx = tid; idx < mm; idx += kT) {
+    for (long idx = tid; idx < mm; idx += NT) {
       const int r = (int)(idx / m), cc = (int)(idx % m);
       W[(long)(k + 1 + r) * n + (k + 1 + cc)] -= 2.0 * (u[r] * q[cc] + q[r] * u[cc]);
     }
@@ -110,7 +113,7 @@ __global__ __launch_bounds__(kT) void syev_kernel(int n, const double* __restric
       e[k] = alpha;
     }
     __syncthreads();
-    for (int r = tid; r < m; r += kT) W[(long)(k + 1 + r) * n + k] = u[r];
+    for (int r = tid; r < m; r += NT) W[(long)(k + 1 + r) * n + k] = u[r];
     __syncthreads();
   }
   if (tid == 0) {
@@ -122,28 +125,28 @@ __global__ __launch_bounds__(kT) void syev_kernel(int n, const double* __restric
     e[n - 1] = 0.0;
   }
   // ---- Q = H_0 H_1 ... H_{n-3}, accumulated backwards into Zr (row-major) ----
-  for (long i = tid; i < nn; i += kT) Zr[i] = ((i / n) == (i % n)) ? 1.0 : 0.0;
+  for (long i = tid; i < nn; i += NT) Zr[i] = ((i / n) == (i % n)) ? 1.0 : 0.0;
   __syncthreads();
   for (int k = n - 3; k >= 0; --k) {
     const int m = n - k - 1;
-    for (int r = tid; r < m; r += kT) u[r] = W[(long)(k + 1 + r) * n + k];
+    for (int r = tid; r < m; r += NT) u[r] = W[(long)(k + 1 + r) * n + k];
     __syncthreads();
     // t_c = sum_r u_r Z[k+1+r][k+1+c]
-    for (int cc = tid; cc < m; cc += kT) {
+    for (int cc = tid; cc < m; cc += NT) {
       double acc = 0.0;
       for (int r = 0; r < m; ++r) acc += u[r] * Zr[(long)(k + 1 + r) * n + (k + 1 + cc)];
       q[cc] = acc;
     }
     __syncthreads();
     const long mm = (long)m * m;
-    for (long idx = tid; idx < mm; idx += kT) {
+    for (long idx = tid; idx < mm; idx += NT) {
       const int r = (int)(idx / m), cc = (int)(idx % m);
       Zr[(long)(k + 1 + r) * n + (k + 1 + cc)] -= 2.0 * u[r] * q[cc];
     }
     __syncthreads();
   }
   // column-major copy for the rotation phase: W[c*n + r] = Zr[r*n + c]
-  for (long idx = tid; idx < nn; idx += kT) {
+  for (long idx = tid; idx < nn; idx += NT) {
     const long r = idx / n, cc = idx % n;
     W[cc * n + r] = Zr[idx];
   }
@@ -209,7 +212,7 @@ __global__ __launch_bounds__(kT) void syev_kernel(int n, const double* __restric
       __syncthreads();
       if (done) break;
       // apply rotations i = mm-1, mm-2, ... to columns (i, i+1) of Z, one row per thread
-      for (int row = tid; row < n; row += kT) {
+      for (int row = tid; row < n; row += NT) {
         for (int t = 0; t < nrot; ++t) {
           const int i = mm - 1 - t;
           const double c = cs[t], s = sn[t];
@@ -239,8 +242,8 @@ __global__ __launch_bounds__(kT) void syev_kernel(int n, const double* __restric
     }
   }
   __syncthreads();
-  for (int i = tid; i < n; i += kT) w[i] = d[perm[i]];
-  for (long idx = tid; idx < nn; idx += kT) {
+  for (int i = tid; i < n; i += NT) w[i] = d[perm[i]];
+  for (long idx = tid; idx < nn; idx += NT) {
     const long r = idx / n, cc = idx % n;
     Z[idx] = Zc[(long)perm[cc] * n + r];
   }
@@ -645,7 +648,10 @@ void small_syev(int n, const double* A, double* w, double* Z, hipStream_t s, dou
   if (n < 1 || n > kMaxN) throw InvalidArg("small_syev: n out of range");
   double* ws = scratch;
   if (!ws) PPW_HIP(hipMalloc(&ws, sizeof(double) * 2 * (size_t)n * n));
-  syev_kernel<<<1, kT, 0, s>>>(n, A, w, Z, ws, ws + (size_t)n * n);
+  if (n <= 64)
+    syev_kernel<64><<<1, 64, 0, s>>>(n, A, w, Z, ws, ws + (size_t)n * n);
+  else
+    syev_kernel<kT><<<1, kT, 0, s>>>(n, A, w, Z, ws, ws + (size_t)n * n);
   hipError_t e = hipGetLastError();
   if (!scratch) {
     (void)hipStreamSynchronize(s);

@@ -77,7 +77,7 @@ def test_gemm_layouts(B, fp32, M, N, K, KB, nb, tA, tB):
         np.testing.assert_allclose(got, exp, rtol=(2e-5 if fp32 else 0), atol=tol)
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 5, 37, 130, 400])
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 37, 64, 65, 130, 400])
 def test_small_syev(B, n):
     rng = np.random.default_rng(n)
     X = rng.standard_normal((n, n))
