@@ -94,6 +94,8 @@ typedef struct {
   int32_t device;           /* HIP device ordinal */
   void* stream;             /* hipStream_t to run on (NULL: a stream owned by the handle) */
   uint64_t seed;            /* start-block perturbation seed */
+  int32_t tda;              /* nonzero: Tamm-Dancoff problem, B = 0 (A z = omega S z), the
+                               A-only variant of the error-analysis subsection (Discussion) */
 } pp_options;
 
 #define PP_MAX_ROOTS 64

@@ -40,7 +40,7 @@ class pp_options(C.Structure):
                 ("tol", C.c_double), ("block", C.c_int32), ("krylov_steps", C.c_int32),
                 ("max_basis", C.c_int32), ("max_cycles", C.c_int32), ("d_clamp", C.c_double),
                 ("hbm_budget", C.c_uint64), ("device", C.c_int32), ("stream", C.c_void_p),
-                ("seed", C.c_uint64)]
+                ("seed", C.c_uint64), ("tda", C.c_int32)]
 
 
 class pp_solve_info(C.Structure):

@@ -73,6 +73,7 @@ pp_status pp_setup(const pp_system* sys, const pp_options* opt_in, pp_handle** o
     p.store_amplitudes = opt.store_amplitudes;
     p.strip_rows = opt.strip_rows;
     p.want_f32 = opt.precision == PP_FP32;
+    p.tda = opt.tda != 0;
     p.budget = opt.hbm_budget;
     p.device = opt.device;
     p.stream = static_cast<hipStream_t>(opt.stream);

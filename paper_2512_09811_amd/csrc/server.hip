@@ -403,6 +403,7 @@ class Server {
       p.store_amplitudes = r->store ? 1 : 0;
       p.strip_rows = r->strip_rows;
       p.want_f32 = opt_.precision == PP_FP32;
+      p.tda = opt_.tda != 0;
       p.budget = r->bytes;
       p.device = opt_.device;
       c = setup_context(p);

@@ -219,6 +219,8 @@ Context* setup_context(const SetupParams& p) {
     }
     diag_assemble(o, v, p.order, c->eps_o, c->eps_v, coul, exch, c->Gv, c->Ev, c->Go, c->Eo, c->dA, c->dB, c->dS,
                   s);
+    c->tda = p.tda;
+    if (c->tda) PPW_HIP(hipMemsetAsync(c->dB, 0, sizeof(double) * N, s));
     c->R = c->arena.alloc<double>((size_t)o * c->ns * X * v, "ring operand");
     build_ring_operand(c->Bov, c->Lam, o, v, X, c->R, s);
     if (p.want_f32 && p.order >= 1) {
@@ -622,10 +624,26 @@ void sigma_reserve(Context& c, int k, int precision) {
 
 namespace {
 
+void emit_products(Context& c, int order, int k, int prec, const double* V, double* AV, double* BV, double* SV,
+                   hipStream_t s, std::vector<Step>* tape);
+
 // One product pass of k vectors (contractions in the given precision, then the FP64
 // diagonal term and combination), launched on s or recorded on a tape.
 void emit_pass(Context& c, int order, int k, int prec, const double* V, double* AV, double* BV, double* SV,
                hipStream_t s, std::vector<Step>* tape) {
+  emit_products(c, order, k, prec, V, AV, BV, SV, s, tape);
+  if (c.tda) {
+    // Tamm-Dancoff: B = 0
+    Emit<double> em;
+    em.s = s;
+    em.tape = tape;
+    const size_t bytes = sizeof(double) * (size_t)k * c.N;
+    em.call([=](hipStream_t st) { PPW_HIP(hipMemsetAsync(BV, 0, bytes, st)); });
+  }
+}
+
+void emit_products(Context& c, int order, int k, int prec, const double* V, double* AV, double* BV, double* SV,
+                   hipStream_t s, std::vector<Step>* tape) {
   const int o = c.o, v = c.v;
   const long N = c.N, kN = (long)k * N;
   const double *eo = c.eps_o, *ev = c.eps_v;

@@ -204,3 +204,31 @@ def test_window_survey_completeness(P, precision):
                                            err_msg=f"window {w['omega0']:.4f}")
                 assert np.all(infos[k]["converged"] == 1)
             print(f"[survey] windows {b0}..{b0 + len(part) - 1} ok", flush=True)
+
+
+def test_window_tda(P):
+    """Tamm-Dancoff windows (B = 0, A x = omega S x) at second order against the oracle."""
+    sys = gen(7, 12, 40, 100)
+    A, B, S = dense.assemble(sys, 2)
+    for omega0, nr in ((0.45, 6), (1.1, 6)):
+        with P.Handle.from_system(sys, order=2, tda=1) as h:
+            e, vec, f, info = h.window_solve(omega0, nr)
+        e_ref, X_ref, Y_ref, f_ref = pencil.window_solve(A, 0.0 * B, S, sys.dip, omega0, nr)
+        np.testing.assert_allclose(e, e_ref, rtol=0, atol=1e-8)
+        big = f_ref >= 1e-4 * f_ref.max()
+        np.testing.assert_allclose(f[big], f_ref[big], rtol=1e-5)
+        assert np.abs(vec[:, 1]).max() < 1e-10  # Y = 0
+        assert np.all(info["converged"] == 1)
+
+
+def test_window_order0_exact(P):
+    """Zeroth order: roots are the orbital-energy differences, f = (4/3) D sum_x mu_x^2."""
+    sys = gen(5, 6, 22, 40)
+    D = (sys.eps_v[None, :] - sys.eps_o[:, None]).ravel()
+    mu2 = np.sum(sys.dip.reshape(3, -1) ** 2, axis=0)
+    with P.Handle.from_system(sys, order=0) as h:
+        e, vec, f, info = h.window_solve(1.0, 6)
+    idx = np.argsort(np.abs(D - 1.0), kind="stable")[:6]
+    idx = idx[np.argsort(D[idx])]
+    np.testing.assert_allclose(e, D[idx], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(f, (4.0 / 3.0) * D[idx] * mu2[idx], rtol=1e-10, atol=1e-14)

@@ -286,3 +286,17 @@ def test_first_order_rows_match_dense_assembly():
     AV, BV = columns.first_order_rows(sys_.eps, sys_.o, sys_.v, sys_.B_ov, rows, Boo_i, Bvv_a, V)
     np.testing.assert_allclose(AV, (V @ A.T)[:, rows], rtol=0, atol=1e-14)
     np.testing.assert_allclose(BV, (V @ B.T)[:, rows], rtol=0, atol=1e-14)
+
+
+def test_tda_pencil_matches_generalized_eigh():
+    """Tamm-Dancoff (B = 0): the pencil route reduces to the generalized symmetric
+    problem A x = omega S x (library routine scipy.linalg.eigh(A, S))."""
+    sys_ = gen(4, 4, 9, 20, b_scale=0.4)
+    A, B, S = dense.assemble(sys_, 2)
+    w_ref, Xr = sla.eigh(A, S)
+    for w0, nr in ((0.6, 4), (1.3, 5)):
+        e, X, Y, f = pencil.window_solve(A, 0.0 * B, S, sys_.dip, w0, nr)
+        idx = np.sort(np.argsort(np.abs(w_ref - w0), kind="stable")[:nr])
+        np.testing.assert_allclose(e, w_ref[idx], rtol=0, atol=1e-12)
+        assert np.abs(Y).max() < 1e-13
+        np.testing.assert_allclose(np.einsum("nq,nm,mq->q", X, S, X), 1.0, atol=1e-12)
