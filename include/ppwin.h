@@ -96,6 +96,10 @@ typedef struct {
   uint64_t seed;            /* start-block perturbation seed */
   int32_t tda;              /* nonzero: Tamm-Dancoff problem, B = 0 (A z = omega S z), the
                                A-only variant of the error-analysis subsection (Discussion) */
+  int32_t correlated_f;     /* nonzero: oscillator strengths from the property vector
+                               F_k = <[q_k, mu]> over the MP2 ground state (Theory section,
+                               the numerator of the propagator), which through second order is
+                               the metric applied to mu: F = S mu (0: F = mu, zeroth order) */
 } pp_options;
 
 #define PP_MAX_ROOTS 64
@@ -132,7 +136,8 @@ pp_status pp_sigma(pp_handle* h, int32_t order, int32_t m, const double* X, doub
 /* Roots of M z = omega Sigma z nearest omega0 on the positive branch, at the
  * handle's setup order: energies[n_roots] ascending (Ha); vectors
  * [n_roots][2][n_occ][n_vir] with X^T S X - Y^T S Y = 1 (nullable); osc
- * [n_roots] dipole oscillator strengths f = (2/3) omega sum_x (sqrt(2) mu^x.(X+Y))^2
+ * [n_roots] dipole oscillator strengths f = (2/3) omega sum_x (sqrt(2) F^x.(X+Y))^2 with
+ * F = mu (or F = S mu with opt->correlated_f)
  * (nullable; needs dip at setup); info (nullable).  1 <= n_roots <= min(64, N). */
 pp_status pp_window_solve(pp_handle* h, double omega0, int32_t n_roots, double* energies, double* vectors,
                           double* osc, pp_solve_info* info);
@@ -177,6 +182,15 @@ uint64_t pp_device_bytes(const pp_handle* h);
 
 /* Frees every device allocation of the handle.  NULL is accepted. */
 pp_status pp_destroy(pp_handle* h);
+
+/* Broadened absorption spectrum from window roots (Results section: the spectra are
+ * the roots' oscillator strengths broadened in frequency): for each grid point w_g,
+ *     out[g] = sum_k osc[k] * (eta/pi) / ((w_g - energies[k])^2 + eta^2)
+ * (a Lorentzian of half width eta per root; its integral over w is osc[k]).  Host
+ * pointers: energies[n], osc[n], omega[n_omega], out[n_omega].  Host-only (no device
+ * work); PP_EINVAL for n < 0, n_omega < 0, eta <= 0 or NULL arrays with positive sizes. */
+pp_status pp_spectrum(int32_t n, const double* energies, const double* osc, int32_t n_omega, const double* omega,
+                      double eta, double* out);
 
 /* ------------------------------------------------------------------------
  * Serving: a persistent request loop for window solves of differing systems.

@@ -156,6 +156,19 @@ class MP2Response:
         QR = np.einsum("kxy,y->kx", Qs, R)
         return QtL @ QpR.T - (QptL @ QR.T).T
 
+    def property_vector(self, d):
+        """(F0, F2): F_k = <[Q_k, D]> for the one-body operator D = sum_pq d_pq p^+ q
+        (the property vector of the propagator's numerator, Theory section), over the
+        normalized |0> + Psi1 to second order.  The first-order terms <0|[Q,D]|Psi1> + c.c.
+        are kept (they vanish: [Q, D] is one-body and Psi1 has only doubles)."""
+        r, p = self.ref, self.psi1
+        D = np.einsum("pq,pqxy->xy", d, self.E)
+        C = np.einsum("kxy,yz->kxz", self.dex, D) - np.einsum("xy,kyz->kxz", D, self.dex)
+        F0 = np.einsum("x,kxy,y->k", r, C, r)
+        F1 = np.einsum("x,kxy,y->k", p, C, r) + np.einsum("x,kxy,y->k", r, C, p)
+        F2 = np.einsum("x,kxy,y->k", p, C, p) - (p @ p) * F0
+        return F0, F1 + F2
+
     # --- matrices by order ---------------------------------------------------
     def metric(self):
         """(S0, S2)."""

@@ -71,18 +71,22 @@ def select_window(omega, omega0, n_roots):
     return np.sort(pick)
 
 
-def oscillator_strengths(omega, X, Y, dip):
-    """f_k = (2/3) omega_k sum_x (sqrt(2) mu^x . (X+Y)_k)^2; dip is [3][o][v]."""
+def oscillator_strengths(omega, X, Y, dip, metric=None):
+    """f_k = (2/3) omega_k sum_x (sqrt(2) F^x . (X+Y)_k)^2 with the property vector
+    F^x = mu^x (zeroth order), or F^x = S mu^x when the metric S is given (the property
+    vector over the MP2 ground state through second order); dip is [3][o][v]."""
     mu = dip.reshape(3, -1)
+    if metric is not None:
+        mu = mu @ metric.T
     T = np.sqrt(2.0) * (mu @ (X + Y))
     return (2.0 / 3.0) * omega * np.sum(T * T, axis=0)
 
 
-def window_solve(A, B, S, dip, omega0, n_roots):
+def window_solve(A, B, S, dip, omega0, n_roots, correlated_f=False):
     """Reference result of a window solve: (energies, X, Y, f) for the window."""
     omega, X, Y = solve_all(A, B, S)
     idx = select_window(omega, omega0, n_roots)
-    f = oscillator_strengths(omega[idx], X[:, idx], Y[:, idx], dip)
+    f = oscillator_strengths(omega[idx], X[:, idx], Y[:, idx], dip, S if correlated_f else None)
     return omega[idx], X[:, idx], Y[:, idx], f
 
 

@@ -40,7 +40,7 @@ class pp_options(C.Structure):
                 ("tol", C.c_double), ("block", C.c_int32), ("krylov_steps", C.c_int32),
                 ("max_basis", C.c_int32), ("max_cycles", C.c_int32), ("d_clamp", C.c_double),
                 ("hbm_budget", C.c_uint64), ("device", C.c_int32), ("stream", C.c_void_p),
-                ("seed", C.c_uint64), ("tda", C.c_int32)]
+                ("seed", C.c_uint64), ("tda", C.c_int32), ("correlated_f", C.c_int32)]
 
 
 class pp_solve_info(C.Structure):
@@ -132,6 +132,8 @@ def lib() -> C.CDLL:
         L.ppint_cholesky.restype = C.c_int
         L.ppint_products.argtypes = [vp, i32, i32, vp, vp, vp, vp, i32]
         L.ppint_products.restype = C.c_int
+        L.pp_spectrum.argtypes = [i32, vp, vp, i32, vp, dbl, vp]
+        L.pp_spectrum.restype = C.c_int
         L.pp_server_create.argtypes = [C.POINTER(pp_options), u64, i32, C.POINTER(vp)]
         L.pp_server_create.restype = C.c_int
         L.pp_server_submit.argtypes = [vp, C.POINTER(pp_system), dbl, i32, C.POINTER(u64)]
@@ -344,6 +346,17 @@ def syev(A, w, Z):
 
 def cholesky(A, L_):
     _check(lib().ppint_cholesky(A.shape[0], A.data_ptr(), L_.data_ptr()))
+
+
+def spectrum(energies, osc, omega, eta: float) -> np.ndarray:
+    """Lorentzian-broadened oscillator-strength spectrum on the grid omega (pp_spectrum)."""
+    e, f, w = _f64(energies).ravel(), _f64(osc).ravel(), _f64(omega).ravel()
+    if e.shape != f.shape:
+        raise ValueError("energies and osc must have the same length")
+    out = np.empty_like(w)
+    _check(lib().pp_spectrum(len(e), e.ctypes.data, f.ctypes.data, len(w), w.ctypes.data, float(eta),
+                             out.ctypes.data))
+    return out
 
 
 class Server:

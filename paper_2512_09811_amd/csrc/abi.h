@@ -80,6 +80,7 @@ inline SolveOptions solve_options(const pp_options& o) {
   so.max_cycles = o.max_cycles;
   so.d_clamp = o.d_clamp;
   so.seed = o.seed;
+  so.correlated_f = o.correlated_f;
   return so;
 }
 

@@ -197,6 +197,25 @@ pp_status pp_destroy(pp_handle* h) {
   return st;
 }
 
+pp_status pp_spectrum(int32_t n, const double* energies, const double* osc, int32_t n_omega, const double* omega,
+                      double eta, double* out) {
+  std::string err;
+  return guarded(&err, [&] {
+    if (n < 0 || n_omega < 0) throw ppw::InvalidArg("negative size");
+    if (!(eta > 0.0) || !std::isfinite(eta)) throw ppw::InvalidArg("eta must be positive");
+    if ((n > 0 && (!energies || !osc)) || (n_omega > 0 && (!omega || !out))) throw ppw::InvalidArg("NULL array");
+    const double c = eta / 3.14159265358979323846;
+    for (int g = 0; g < n_omega; ++g) {
+      double acc = 0.0;
+      for (int k = 0; k < n; ++k) {
+        const double d = omega[g] - energies[k];
+        acc += osc[k] * c / (d * d + eta * eta);
+      }
+      out[g] = acc;
+    }
+  });
+}
+
 const char* pp_status_string(pp_status s) {
   switch (s) {
     case PP_OK: return "PP_OK";

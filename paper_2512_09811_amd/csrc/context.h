@@ -159,6 +159,8 @@ struct Context {
   // inputs (device)
   double *eps_o = nullptr, *eps_v = nullptr;
   double *Bov = nullptr, *Boo = nullptr, *Bvv = nullptr, *dip = nullptr;
+  // correlated property vector S mu (order 2 with dipoles; equals dip below order 2)
+  double* dipS = nullptr;
   // derived layouts
   double* BovLam = nullptr;  // [ns][naux][N]: Bov, then Lambda at order 2
   double* Lam = nullptr;     // Lambda_P,ia = sum_kc tau_ik^ac B_P,kc

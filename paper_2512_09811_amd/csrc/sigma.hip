@@ -221,6 +221,24 @@ Context* setup_context(const SetupParams& p) {
                   s);
     c->tda = p.tda;
     if (c->tda) PPW_HIP(hipMemsetAsync(c->dB, 0, sizeof(double) * N, s));
+    if (c->dip && p.order >= 2) {
+      // property vector over the MP2 ground state through second order: S mu, with
+      // S V = V - Go V - V Gv (the metric), for the three dipole components
+      c->dipS = c->arena.alloc<double>((size_t)3 * N, "dip S mu");
+      PPW_HIP(hipMemcpyAsync(c->dipS, c->dip, sizeof(double) * 3 * N, hipMemcpyDeviceToDevice, s));
+      GemmDesc g1 = gd(o, v, o, 0, o, 0, v, v);  // - Go mu_x
+      g1.nb1 = 3;
+      g1.sB1 = N;
+      g1.sC1 = N;
+      gemm_f64(g1, -1.0, c->Go, c->dip, 1.0, c->dipS, s, c->ws);
+      GemmDesc g2 = gd(o, v, v, 0, v, 0, v, v);  // - mu_x Gv
+      g2.nb1 = 3;
+      g2.sA1 = N;
+      g2.sC1 = N;
+      gemm_f64(g2, -1.0, c->dip, c->Gv, 1.0, c->dipS, s, c->ws);
+    } else {
+      c->dipS = c->dip;
+    }
     c->R = c->arena.alloc<double>((size_t)o * c->ns * X * v, "ring operand");
     build_ring_operand(c->Bov, c->Lam, o, v, X, c->R, s);
     if (p.want_f32 && p.order >= 1) {

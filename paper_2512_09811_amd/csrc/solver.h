@@ -17,6 +17,7 @@ struct SolveOptions {
   int max_cycles = 200;
   double d_clamp = 1e-4;
   unsigned long long seed = 0;
+  int correlated_f = 0;   // oscillator strengths from the property vector S mu (else mu)
 };
 
 // One window solve's request for A, B and S products of k orthonormal vectors V

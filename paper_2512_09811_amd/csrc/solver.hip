@@ -1184,7 +1184,8 @@ void Solver::run(double* energies, double* vectors, double* osc, pp_solve_info* 
   }
   if (osc) {
     // T[x][j] = sum_ia dip[x][ia] u_j[ia]
-    gemm(gd(3, r, (int)N_, 0, N_, 1, N_, r), 1.0, c_.dip, T1_, 0.0, tmp_);
+    const double* F = (opt_.correlated_f && c_.dipS) ? c_.dipS : c_.dip;
+    gemm(gd(3, r, (int)N_, 0, N_, 1, N_, r), 1.0, F, T1_, 0.0, tmp_);
     std::vector<double> thsel(r);
     for (int q = 0; q < r; ++q) thsel[q] = R.th[sel[q]];
     upload(th2_, thsel);

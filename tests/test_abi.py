@@ -50,3 +50,23 @@ def test_host_only_helpers(lib):
     lib.pp_status_string.restype = ctypes.c_char_p
     for code in range(7):
         assert lib.pp_status_string(code)
+
+
+def test_spectrum_host_entry():
+    """pp_spectrum (host-only): each root contributes a unit-area Lorentzian times its
+    oscillator strength; the integral over a wide grid is the sum of strengths, an
+    isolated peak has height f/(pi eta), and bad arguments are rejected."""
+    import numpy as np
+    import paper_2512_09811_amd as P
+    e = np.array([0.5, 0.9, 0.905, 2.0])
+    f = np.array([0.1, 0.02, 0.3, 0.05])
+    eta = 2e-3
+    w = np.linspace(-50.0, 60.0, 2_000_001)
+    s = P.spectrum(e, f, w, eta)
+    integral = np.sum(0.5 * (s[1:] + s[:-1]) * np.diff(w))
+    tails = (f.sum() * 2 * eta / np.pi) * (1 / 50.0)  # the Lorentzian mass outside the grid, to first order
+    assert abs(integral - f.sum()) < tails
+    peak = P.spectrum(e, f, np.array([2.0]), eta)[0]
+    assert abs(peak - f[3] / (np.pi * eta)) < 1e-3 * peak
+    with pytest.raises(P.PPError):
+        P.spectrum(e, f, w[:10], 0.0)

@@ -232,3 +232,24 @@ def test_window_order0_exact(P):
     idx = idx[np.argsort(D[idx])]
     np.testing.assert_allclose(e, D[idx], rtol=0, atol=1e-12)
     np.testing.assert_allclose(f, (4.0 / 3.0) * D[idx] * mu2[idx], rtol=1e-10, atol=1e-14)
+
+
+def test_window_correlated_property_vector(P):
+    """Oscillator strengths from the correlated property vector F = S mu (second order)
+    against the oracle; below second order S = 1 and they equal the plain ones."""
+    sys = gen(7, 12, 40, 100)
+    A, B, S = dense.assemble(sys, 2)
+    with P.Handle.from_system(sys, order=2, correlated_f=1) as h:
+        e, vec, f, info = h.window_solve(1.1, 8)
+    e_ref, X_ref, Y_ref, f_ref = pencil.window_solve(A, B, S, sys.dip, 1.1, 8, correlated_f=True)
+    _, _, _, f_plain = pencil.window_solve(A, B, S, sys.dip, 1.1, 8)
+    np.testing.assert_allclose(e, e_ref, rtol=0, atol=1e-8)
+    big = f_ref >= 1e-4 * f_ref.max()
+    np.testing.assert_allclose(f[big], f_ref[big], rtol=1e-5)
+    assert np.abs(f_ref - f_plain).max() > 1e-6 * f_ref.max()  # the correction is visible
+    sys1 = gen(1, 8, 24, 64)
+    with P.Handle.from_system(sys1, order=1, correlated_f=1) as h:
+        e1, _, f1, _ = h.window_solve(0.5, 6)
+    with P.Handle.from_system(sys1, order=1) as h:
+        e0, _, f0, _ = h.window_solve(0.5, 6)
+    np.testing.assert_allclose(f1, f0, rtol=1e-12)

@@ -300,3 +300,21 @@ def test_tda_pencil_matches_generalized_eigh():
         np.testing.assert_allclose(e, w_ref[idx], rtol=0, atol=1e-12)
         assert np.abs(Y).max() < 1e-13
         np.testing.assert_allclose(np.einsum("nq,nm,mq->q", X, S, X), 1.0, atol=1e-12)
+
+
+@pytest.mark.parametrize("no,nv,seed", [(2, 3, 1), (3, 3, 2), (2, 4, 3)])
+def test_p6_property_vector_is_metric_times_dipole(no, nv, seed):
+    """F_k = <[q_k, D]> over the MP2 ground state (brute force, D with oo, ov and vv
+    blocks) equals S d_ov through second order: the oo and vv blocks of D drop out and
+    the correlated property vector is the metric applied to the zeroth-order one."""
+    eps, _, V = spinorb.spinless_system(seed, no, nv)
+    r = fockspace.MP2Response(eps, no, V)
+    n = no + nv
+    Z = np.random.default_rng(seed + 50).standard_normal((n, n))
+    d = 0.5 * (Z + Z.T)
+    F0, F2 = r.property_vector(d)
+    S0, S2 = r.metric()
+    d_ov = np.array([d[i, no + a] for i in range(no) for a in range(nv)])
+    assert np.abs(F2).max() > 1e-5
+    np.testing.assert_allclose(F0, d_ov, atol=1e-14)
+    np.testing.assert_allclose(F2, S2 @ d_ov, atol=1e-13)
