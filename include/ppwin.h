@@ -183,6 +183,14 @@ uint64_t pp_device_bytes(const pp_handle* h);
 /* Frees every device allocation of the handle.  NULL is accepted. */
 pp_status pp_destroy(pp_handle* h);
 
+/* Excitonic density of states of the Discussion section: for each energy bin
+ * [edges[b], edges[b+1]) the number of particle-hole pairs ia whose orbital-energy
+ * difference eps_a - eps_i falls in it (counts[b]) and the sum of their squared
+ * transition dipoles sum_x (mu^x_ia)^2 (mu2[b]; zero without dip).  edges[n_bins+1]
+ * ascending (Ha), counts and mu2 [n_bins] (mu2 nullable); host pointers.  Computed
+ * on the device from the handle's copies of eps and the dipoles. */
+pp_status pp_exciton_dos(pp_handle* h, int32_t n_bins, const double* edges, double* counts, double* mu2);
+
 /* Broadened absorption spectrum from window roots (Results section: the spectra are
  * the roots' oscillator strengths broadened in frequency): for each grid point w_g,
  *     out[g] = sum_k osc[k] * (eta/pi) / ((w_g - energies[k])^2 + eta^2)

@@ -101,3 +101,18 @@ def variance(Mop, x):
     x = x / np.linalg.norm(x)
     Ax = Mop @ x
     return float(Ax @ Ax - (x @ Ax) ** 2)
+
+
+def exciton_dos(eps_o, eps_v, dip, edges):
+    """Excitonic density of states (Discussion section): per half-open energy bin
+    [edges[b], edges[b+1]) the number of particle-hole pairs with eps_a - eps_i inside,
+    and the sum of their squared transition dipoles sum_x (mu^x_ia)^2."""
+    dE = (eps_v[None, :] - eps_o[:, None]).ravel()
+    mu2 = np.sum(dip.reshape(3, -1) ** 2, axis=0) if dip is not None else np.zeros_like(dE)
+    counts = np.zeros(len(edges) - 1)
+    weights = np.zeros(len(edges) - 1)
+    for b in range(len(edges) - 1):
+        inside = (dE >= edges[b]) & (dE < edges[b + 1])
+        counts[b] = np.count_nonzero(inside)
+        weights[b] = mu2[inside].sum()
+    return counts, weights

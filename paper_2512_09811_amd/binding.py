@@ -132,6 +132,8 @@ def lib() -> C.CDLL:
         L.ppint_cholesky.restype = C.c_int
         L.ppint_products.argtypes = [vp, i32, i32, vp, vp, vp, vp, i32]
         L.ppint_products.restype = C.c_int
+        L.pp_exciton_dos.argtypes = [vp, i32, vp, vp, vp]
+        L.pp_exciton_dos.restype = C.c_int
         L.pp_spectrum.argtypes = [i32, vp, vp, i32, vp, dbl, vp]
         L.pp_spectrum.restype = C.c_int
         L.pp_server_create.argtypes = [C.POINTER(pp_options), u64, i32, C.POINTER(vp)]
@@ -303,6 +305,14 @@ class Handle:
                             residual=np.array(info.residual[:n_roots]),
                             converged=np.array(info.converged[:n_roots]), status=st))
         return e, vec, f, out
+
+    def exciton_dos(self, edges):
+        """(counts, mu2) per energy bin of the particle-hole energies eps_a - eps_i."""
+        ed = _f64(edges).ravel()
+        nb = len(ed) - 1
+        counts, mu2 = np.empty(nb), np.empty(nb)
+        _check(lib().pp_exciton_dos(self.h, nb, ed.ctypes.data, counts.ctypes.data, mu2.ctypes.data), self.h)
+        return counts, mu2
 
     def mp2_energy(self) -> float:
         return lib().pp_mp2_energy(self.h)

@@ -197,6 +197,42 @@ pp_status pp_destroy(pp_handle* h) {
   return st;
 }
 
+pp_status pp_exciton_dos(pp_handle* h, int32_t n_bins, const double* edges, double* counts, double* mu2) {
+  if (!h || !h->ctx) return PP_EINVAL;
+  return guarded(&h->err, [&] {
+    if (n_bins < 1 || n_bins > (1 << 20)) throw ppw::InvalidArg("n_bins out of range");
+    if (!edges || !counts) throw ppw::InvalidArg("edges and counts must not be NULL");
+    for (int b = 0; b < n_bins; ++b)
+      if (!(edges[b] < edges[b + 1])) throw ppw::InvalidArg("edges must be strictly ascending");
+    ppw::Context& c = *h->ctx;
+    PPW_HIP(hipSetDevice(c.device));
+    double *d_edges = nullptr, *d_out = nullptr;
+    PPW_HIP(hipMalloc(&d_edges, sizeof(double) * (n_bins + 1)));
+    hipError_t e = hipMalloc(&d_out, sizeof(double) * 2 * n_bins);
+    if (e != hipSuccess) {
+      (void)hipFree(d_edges);
+      PPW_HIP(e);
+    }
+    std::vector<double> out(2 * (size_t)n_bins);
+    try {
+      PPW_HIP(hipMemcpyAsync(d_edges, edges, sizeof(double) * (n_bins + 1), hipMemcpyHostToDevice, c.stream));
+      ppw::exciton_dos(c.o, c.v, c.eps_o, c.eps_v, c.dip, d_edges, n_bins, d_out, c.stream);
+      PPW_HIP(hipMemcpyAsync(out.data(), d_out, sizeof(double) * 2 * n_bins, hipMemcpyDeviceToHost, c.stream));
+      PPW_HIP(hipStreamSynchronize(c.stream));
+    } catch (...) {
+      (void)hipFree(d_edges);
+      (void)hipFree(d_out);
+      throw;
+    }
+    (void)hipFree(d_edges);
+    (void)hipFree(d_out);
+    for (int b = 0; b < n_bins; ++b) {
+      counts[b] = out[2 * b];
+      if (mu2) mu2[b] = out[2 * b + 1];
+    }
+  });
+}
+
 pp_status pp_spectrum(int32_t n, const double* energies, const double* osc, int32_t n_omega, const double* omega,
                       double eta, double* out) {
   std::string err;

@@ -51,6 +51,11 @@ void build_ring_operand(const double* Bov, const double* Lam, int o, int v, int 
 // y = alpha*x + beta*y (n elements), and conversions.
 void axpby(long n, double alpha, const double* x, double beta, double* y, hipStream_t s);
 void to_f32(long n, const double* x, float* y, hipStream_t s);
+// Excitonic density of states: out[2b] = #pairs with eps_a - eps_i in [edges[b], edges[b+1]),
+// out[2b+1] = their sum of squared dipoles (dip nullable).  Device pointers.
+void exciton_dos(int o, int v, const double* eo, const double* ev, const double* dip, const double* edges,
+                 int n_bins, double* out, hipStream_t s);
+
 void to_f64(long n, const float* x, double* y, hipStream_t s);
 
 // Column statistics of k column-vectors of length n stored [k][n] (row-major per vector):

@@ -217,6 +217,29 @@ __global__ void to_f32_kernel(long n, const double* __restrict__ x, float* __res
     y[i] = (float)x[i];
 }
 
+// one block per bin: pairs with eps_a - eps_i in [lo, hi); sums in a fixed order
+__global__ void dos_kernel(int o, int v, const double* __restrict__ eo, const double* __restrict__ ev,
+                           const double* __restrict__ dip, const double* __restrict__ edges, double* __restrict__ out) {
+  const int b = blockIdx.x;
+  const double lo = edges[b], hi = edges[b + 1];
+  const long N = (long)o * v;
+  double cnt = 0.0, m2 = 0.0;
+  for (long ia = threadIdx.x; ia < N; ia += blockDim.x) {
+    const int i = (int)(ia / v), a = (int)(ia % v);
+    const double d = ev[a] - eo[i];
+    if (d >= lo && d < hi) {
+      cnt += 1.0;
+      if (dip) m2 += dip[ia] * dip[ia] + dip[N + ia] * dip[N + ia] + dip[2 * N + ia] * dip[2 * N + ia];
+    }
+  }
+  cnt = block_sum(cnt);
+  m2 = block_sum(m2);
+  if (threadIdx.x == 0) {
+    out[2 * b] = cnt;
+    out[2 * b + 1] = m2;
+  }
+}
+
 __global__ void to_f64_kernel(long n, const float* __restrict__ x, double* __restrict__ y) {
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
     y[i] = (double)x[i];
@@ -329,6 +352,12 @@ void axpby(long n, double alpha, const double* x, double beta, double* y, hipStr
 
 void to_f32(long n, const double* x, float* y, hipStream_t s) {
   to_f32_kernel<<<grid_for(n), kBlock, 0, s>>>(n, x, y);
+  PPW_LAUNCH_CHECK();
+}
+
+void exciton_dos(int o, int v, const double* eo, const double* ev, const double* dip, const double* edges,
+                 int n_bins, double* out, hipStream_t s) {
+  dos_kernel<<<n_bins, kBlock, 0, s>>>(o, v, eo, ev, dip, edges, out);
   PPW_LAUNCH_CHECK();
 }
 

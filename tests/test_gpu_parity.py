@@ -253,3 +253,17 @@ def test_window_correlated_property_vector(P):
     with P.Handle.from_system(sys1, order=1) as h:
         e0, _, f0, _ = h.window_solve(0.5, 6)
     np.testing.assert_allclose(f1, f0, rtol=1e-12)
+
+
+def test_exciton_dos_matches_oracle(P):
+    """Counts per bin bit-exact (same half-open rule, same FP64 difference), squared-dipole
+    sums to rounding; bins that cut through the spectrum and empty bins included."""
+    sys = gen(7, 12, 40, 100)
+    dE = (sys.eps_v[None, :] - sys.eps_o[:, None]).ravel()
+    edges = np.concatenate([[dE.min() - 0.5], np.linspace(dE.min(), dE.max(), 37), [dE.max() + 1e-12, 9.0]])
+    edges = np.unique(edges)
+    with P.Handle.from_system(sys, order=1) as h:
+        counts, mu2 = h.exciton_dos(edges)
+    c_ref, m_ref = pencil.exciton_dos(sys.eps_o, sys.eps_v, sys.dip, edges)
+    np.testing.assert_array_equal(counts, c_ref)
+    np.testing.assert_allclose(mu2, m_ref, rtol=1e-12, atol=1e-15)

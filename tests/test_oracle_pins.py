@@ -318,3 +318,19 @@ def test_p6_property_vector_is_metric_times_dipole(no, nv, seed):
     assert np.abs(F2).max() > 1e-5
     np.testing.assert_allclose(F0, d_ov, atol=1e-14)
     np.testing.assert_allclose(F2, S2 @ d_ov, atol=1e-13)
+
+
+def test_exciton_dos_invariants():
+    """Every pair lands in exactly one bin of a covering grid; the squared-dipole sums add
+    up to the total; a single pair fills exactly its own bin."""
+    sys_ = gen(2, 6, 21, 30)
+    dE = (sys_.eps_v[None, :] - sys_.eps_o[:, None]).ravel()
+    edges = np.linspace(dE.min(), dE.max() + 1e-9, 13)
+    counts, mu2 = pencil.exciton_dos(sys_.eps_o, sys_.eps_v, sys_.dip, edges)
+    assert counts.sum() == sys_.N
+    np.testing.assert_allclose(mu2.sum(), np.sum(sys_.dip ** 2), rtol=1e-13)
+    one = gen(3, 1, 1, 4)
+    d1 = one.eps_v[0] - one.eps_o[0]
+    c1, m1 = pencil.exciton_dos(one.eps_o, one.eps_v, one.dip, np.array([d1 - 1, d1, d1 + 1]))
+    np.testing.assert_array_equal(c1, [0, 1])
+    np.testing.assert_allclose(m1, [0, np.sum(one.dip ** 2)], rtol=1e-14)
