@@ -96,8 +96,9 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& d, T alpha, const T* _
   static_assert(LA * kThreads == BM * BK && LB * kThreads == BN * BK, "tile/thread mismatch");
   constexpr int SA = AK ? BM * (BK + PK) : BK * (BM + PM);
   constexpr int SB = BKC ? BN * (BK + PK) : BK * (BN + PM);
-  __shared__ T As[2][SA];
-  __shared__ T Bs[2][SB];
+  __shared__ __attribute__((aligned(16))) T As[2][SA];
+  __shared__ __attribute__((aligned(16))) T Bs[2][SB];
+  typedef T pair_t __attribute__((ext_vector_type(2)));
   // element (m, k) of an LDS tile
   auto aidx = [](int m, int k) { return AK ? m * (BK + PK) + k : k * (BM + PM) + m; };
   auto bidx = [](int n, int k) { return BKC ? n * (BK + PK) + k : k * (BN + PM) + n; };
@@ -130,79 +131,150 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& d, T alpha, const T* _
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
-  T ra[LA], rb[LB];
+  // Each thread moves pairs of elements that are adjacent along the contiguous
+  // dimension of the operand: pair p = i * 256 + tid covers (m, k), (m, k + 1) of a
+  // k-contiguous tile or (m, k), (m + 1, k) of an m-contiguous one.
+  constexpr int PA = LA / 2, PB = LB / 2;
+  static_assert(PA * 2 == LA && PB * 2 == LB, "pairs");
+  auto a_pair = [](int p, int& m, int& k) {
+    if (AK) { m = p / (BK / 2); k = 2 * (p % (BK / 2)); }
+    else { m = 2 * (p % (BM / 2)); k = p / (BM / 2); }
+  };
+  auto b_pair = [](int p, int& n, int& k) {
+    if (BKC) { n = p / (BK / 2); k = 2 * (p % (BK / 2)); }
+    else { n = 2 * (p % (BN / 2)); k = p / (BN / 2); }
+  };
+  pair_t ra[PA], rb[PB];
   // Tile base pointers are advanced per iteration (wave-uniform 64-bit); per-element
   // offsets inside a tile are 32-bit (row * ld + k stays below 2^31 for every shape
   // the library issues), which keeps register pressure low enough for 2 waves/SIMD.
   const T* Atile = Ab + (AK ? (long)m0 * d.lda : (long)m0);
   const T* Btile = Bb + (BKC ? (long)n0 * d.ldb : (long)n0);
   const int lda32 = (int)d.lda, ldb32 = (int)d.ldb;
-  auto load = [&](long it) {
-    const int kb = (int)(it / nkt);
-    const int k0 = (int)(it % nkt) * BK;
+  // Pair loads are whole-vector loads when every pair of this tile is in range and
+  // 2-element aligned (decided once per tile; wave-uniform).
+  const int mrem = d.M - m0, nrem = d.N - n0;
+  const bool vec_ok = mrem >= BM && nrem >= BN && (d.lda % 2) == 0 && (d.ldb % 2) == 0 && (d.sAk % 2) == 0 &&
+                      (d.sBk % 2) == 0 && ((uintptr_t)Atile % (2 * sizeof(T))) == 0 &&
+                      ((uintptr_t)Btile % (2 * sizeof(T))) == 0;
+  auto load = [&](int kb, int kt) {
+    const int k0 = kt * BK;
     const T* Ak = Atile + kb * d.sAk + (AK ? (long)k0 : (long)k0 * d.lda);
     const T* Bk = Btile + kb * d.sBk + (BKC ? (long)k0 : (long)k0 * d.ldb);
-    const int mrem = d.M - m0, nrem = d.N - n0, krem = d.K - k0;
+    const int krem = d.K - k0;
+    if (vec_ok && krem >= BK) {
 #pragma unroll
-    for (int i = 0; i < LA; ++i) {
-      const int e = i * kThreads + tid;
-      const int m = AK ? (e / BK) : (e % BM);
-      const int k = AK ? (e % BK) : (e / BM);
-      T v = T(0);
-      if (m < mrem && k < krem) v = Ak[AK ? (m * lda32 + k) : (k * lda32 + m)];
-      ra[i] = v;
-    }
+      for (int i = 0; i < PA; ++i) {
+        int m, k;
+        a_pair(i * kThreads + tid, m, k);
+        ra[i] = *reinterpret_cast<const pair_t*>(Ak + (AK ? (m * lda32 + k) : (k * lda32 + m)));
+      }
 #pragma unroll
-    for (int i = 0; i < LB; ++i) {
-      const int e = i * kThreads + tid;
-      const int n = BKC ? (e / BK) : (e % BN);
-      const int k = BKC ? (e % BK) : (e / BN);
-      T v = T(0);
-      if (n < nrem && k < krem) v = Bk[BKC ? (n * ldb32 + k) : (k * ldb32 + n)];
-      rb[i] = v;
+      for (int i = 0; i < PB; ++i) {
+        int n, k;
+        b_pair(i * kThreads + tid, n, k);
+        rb[i] = *reinterpret_cast<const pair_t*>(Bk + (BKC ? (n * ldb32 + k) : (k * ldb32 + n)));
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < PA; ++i) {
+        int m, k;
+        a_pair(i * kThreads + tid, m, k);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int mh = AK ? m : m + h, kh = AK ? k + h : k;
+          T v = T(0);
+          if (mh < mrem && kh < krem) v = Ak[AK ? (mh * lda32 + kh) : (kh * lda32 + mh)];
+          ra[i][h] = v;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < PB; ++i) {
+        int n, k;
+        b_pair(i * kThreads + tid, n, k);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int nh = BKC ? n : n + h, kh = BKC ? k + h : k;
+          T v = T(0);
+          if (nh < nrem && kh < krem) v = Bk[BKC ? (nh * ldb32 + kh) : (kh * ldb32 + nh)];
+          rb[i][h] = v;
+        }
+      }
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < LA; ++i) {
-      const int e = i * kThreads + tid;
-      const int m = AK ? (e / BK) : (e % BM);
-      const int k = AK ? (e % BK) : (e / BM);
-      As[buf][aidx(m, k)] = ra[i];
+    for (int i = 0; i < PA; ++i) {
+      int m, k;
+      a_pair(i * kThreads + tid, m, k);
+      *reinterpret_cast<pair_t*>(&As[buf][aidx(m, k)]) = ra[i];
     }
 #pragma unroll
-    for (int i = 0; i < LB; ++i) {
-      const int e = i * kThreads + tid;
-      const int n = BKC ? (e / BK) : (e % BN);
-      const int k = BKC ? (e % BK) : (e / BN);
-      Bs[buf][bidx(n, k)] = rb[i];
+    for (int i = 0; i < PB; ++i) {
+      int n, k;
+      b_pair(i * kThreads + tid, n, k);
+      *reinterpret_cast<pair_t*>(&Bs[buf][bidx(n, k)]) = rb[i];
     }
+  };
+  // MFMA operand fragments of k group kk (4 deep) from LDS buffer buf
+  auto frag = [&](int buf, int kk, T (&a)[TM], T (&b)[TN]) {
+    const int kr = kk + (lane >> 4);
+#pragma unroll
+    for (int i = 0; i < TM; ++i) a[i] = As[buf][aidx(wm * WTM + i * 16 + (lane & 15), kr)];
+#pragma unroll
+    for (int j = 0; j < TN; ++j) b[j] = Bs[buf][bidx(wn * WTN + j * 16 + (lane & 15), kr)];
+  };
+  auto mma = [&](const T (&a)[TM], const T (&b)[TN]) {
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) acc[i][j] = Mfma<T>::mma(a[i], b[j], acc[i][j]);
   };
 
   if (it0 < it1) {
-    load(it0);
+    // (outer block, k tile) of the current iteration, stepped without division
+    int kb = (int)(it0 / nkt), kt = (int)(it0 % nkt);
+    load(kb, kt);
     store(0);
     __syncthreads();
     int buf = 0;
     for (long it = it0; it < it1; ++it) {
       const bool more = it + 1 < it1;
-      if (more) load(it + 1);
-#pragma unroll
-      for (int kk = 0; kk < BK; kk += 4) {
-        const int kr = kk + (lane >> 4);
-        T a[TM], b[TN];
-#pragma unroll
-        for (int i = 0; i < TM; ++i) a[i] = As[buf][aidx(wm * WTM + i * 16 + (lane & 15), kr)];
-#pragma unroll
-        for (int j = 0; j < TN; ++j) b[j] = Bs[buf][bidx(wn * WTN + j * 16 + (lane & 15), kr)];
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-          for (int j = 0; j < TN; ++j) acc[i][j] = Mfma<T>::mma(a[i], b[j], acc[i][j]);
+      int nkb = kb, nkt2 = kt + 1;
+      if (nkt2 == nkt) {
+        nkt2 = 0;
+        ++nkb;
       }
+      // fragments alternate between two register sets: the reads of k group g + 1
+      // are in flight while the MFMAs of group g run
+      T a0[TM], b0[TN], a1[TM], b1v[TN];
+      frag(buf, 0, a0, b0);
+      if (more) load(nkb, nkt2);
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 8) {
+        frag(buf, kk + 4, a1, b1v);
+        mma(a0, b0);
+        if (kk + 8 < BK) frag(buf, kk + 8, a0, b0);
+        mma(a1, b1v);
+      }
+      // Issue order for the scheduler: the fragment reads of each following k group
+      // are spread one per MFMA over the first MFMAs of the current group, leaving
+      // the rest of the group to cover their LDS latency.
+#pragma unroll
+      for (int g = 0; g + 1 < BK / 4; ++g) {
+#pragma unroll
+        for (int r = 0; r < TM + TN; ++r) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        }
+        if constexpr (TM * TN > TM + TN) __builtin_amdgcn_sched_group_barrier(0x008, TM * TN - (TM + TN), 0);
+      }
+      __builtin_amdgcn_sched_group_barrier(0x008, TM * TN, 0);
       if (more) store(buf ^ 1);
       __syncthreads();
       buf ^= 1;
+      kb = nkb;
+      kt = nkt2;
     }
   }
 

@@ -39,20 +39,26 @@ def _ref_gemm(A, Bm, M, N, K, KB, nb, tA, lda, sA, sAk, tB, ldb, sB, sBk):
 
 
 @pytest.mark.parametrize("fp32", [False, True])
+@pytest.mark.parametrize("pads", ["odd", "even"])
 @pytest.mark.parametrize("M,N,K,KB,nb,tA,tB", [
     (1, 1, 1, 1, 1, 0, 0), (37, 53, 29, 1, 1, 0, 0), (37, 53, 29, 1, 1, 1, 0), (37, 53, 29, 1, 1, 0, 1),
     (37, 53, 29, 1, 1, 1, 1), (130, 150, 70, 1, 2, 0, 1), (20, 30, 17, 3, 2, 1, 0), (3, 5, 2000, 1, 1, 0, 1),
-    (200, 7, 3000, 2, 1, 1, 1)])
-def test_gemm_layouts(B, fp32, M, N, K, KB, nb, tA, tB):
+    (200, 7, 3000, 2, 1, 1, 1), (260, 300, 100, 2, 2, 0, 0), (260, 300, 100, 2, 2, 1, 0),
+    (260, 300, 100, 2, 2, 0, 1), (260, 300, 100, 2, 2, 1, 1), (96, 80, 64, 1, 1, 0, 1)])
+def test_gemm_layouts(B, fp32, pads, M, N, K, KB, nb, tA, tB):
+    """'odd' pads give strides that are mostly not 2-element aligned (element-wise guarded
+    loads); 'even' pads keep every stride and batch offset 2-element aligned, so interior
+    tiles take the whole-pair load path and the ragged edges the guarded one."""
     rng = np.random.default_rng(M * 7 + N * 13 + K + KB + nb + tA * 3 + tB * 5)
-    lda = (M if tA else K) + 3
-    ldb = (K if tB else N) + 2
+    pa, pb, pak, pbk, psa, psb = (3, 2, 5, 4, 7, 3) if pads == "odd" else (2, 4, 6, 2, 4, 8)
+    lda = (M if tA else K) + pa
+    ldb = (K if tB else N) + pb
     rowsA = K if tA else M
     rowsB = N if tB else K
-    sAk = rowsA * lda + 5
-    sBk = rowsB * ldb + 4
-    sA = KB * sAk + 7
-    sB = KB * sBk + 3
+    sAk = rowsA * lda + pak
+    sBk = rowsB * ldb + pbk
+    sA = KB * sAk + psa
+    sB = KB * sBk + psb
     ldc = N + 1
     sC = M * ldc + 2
     A = rng.standard_normal(nb * sA + 8)
