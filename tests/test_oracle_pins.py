@@ -334,3 +334,65 @@ def test_exciton_dos_invariants():
     c1, m1 = pencil.exciton_dos(one.eps_o, one.eps_v, one.dip, np.array([d1 - 1, d1, d1 + 1]))
     np.testing.assert_array_equal(c1, [0, 1])
     np.testing.assert_allclose(m1, [0, np.sum(one.dip ** 2)], rtol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# Riesz projector (section connecting the method to the Riesz projector)
+# ---------------------------------------------------------------------------
+def _small_pencil(order=2, o=3, v=5, naux=12, seed=21):
+    s = gen(seed, o, v, naux)
+    A, B, S = dense.assemble(s, order)
+    return s, A, B, S
+
+
+@pytest.mark.parametrize("n", [2, 4, 8])
+def test_riesz_trapezoid_filter_closed_form(n):
+    """On every eigenvector of the pencil (both branches) the quadrature of the contour
+    integral is the rational filter 1/(1 + x^(2n)) of x = (omega - c)/r: a closed form of
+    the 2n-node rule, independent of how the shifted systems are solved."""
+    from oracle import riesz
+    _, A, B, S = _small_pencil()
+    omega, X, Y = pencil.solve_all(A, B, S)
+    M, Sig = riesz.pencil_matrices(A, B, S)
+    c = float(omega[len(omega) // 2])
+    r = 0.6 * float(omega[-1] - omega[0]) / 4
+    Z = np.concatenate([np.vstack([X, Y]), np.vstack([Y, X])], axis=1)   # +omega and -omega
+    w = np.concatenate([omega, -omega])
+    PZ = riesz.riesz_apply(M, Sig, Z, c, r, n)
+    rho = 1.0 / (1.0 + ((w - c) / r) ** (2 * n))
+    assert rho.max() > 0.99 and rho.min() < 1e-3            # some roots inside, some far outside
+    np.testing.assert_allclose(PZ, Z * rho, rtol=0, atol=1e-11 * np.abs(Z).max())
+
+
+def test_riesz_projector_limit_is_spectral_projector():
+    """With many nodes and a circle boundary in a spectral gap, the quadrature is the
+    spectral projector: idempotent, with trace = number of enclosed roots."""
+    from oracle import riesz
+    _, A, B, S = _small_pencil(o=2, v=4, naux=10, seed=5)
+    omega, _, _ = pencil.solve_all(A, B, S)
+    M, Sig = riesz.pencil_matrices(A, B, S)
+    gaps = np.diff(omega)
+    g = int(np.argmax(gaps[: len(gaps) // 2 + 1]))
+    c = float(omega[0]) - 1e-3
+    r = 0.5 * (omega[g] + omega[g + 1]) - c
+    P = riesz.riesz_apply(M, Sig, np.eye(M.shape[0]), c, r, 64)
+    inside = int(np.sum(np.abs(omega - c) < r))
+    assert inside == g + 1
+    assert abs(np.trace(P) - inside) < 1e-8
+    np.testing.assert_allclose(P @ P, P, atol=1e-8)
+
+
+@pytest.mark.parametrize("order,omega0,nr", [(1, 0.5, 4), (2, 0.8, 6)])
+def test_riesz_window_solve_equals_definition(order, omega0, nr):
+    """Contour-filtered subspace iteration returns the window of the plain definition
+    (all eigenpairs of the pencil, nearest roots): energies, S-normalised vectors."""
+    from oracle import riesz
+    s = gen(31, 6, 20, 48)
+    A, B, S = dense.assemble(s, order)
+    e_ref, X_ref, Y_ref, _ = pencil.window_solve(A, B, S, s.dip, omega0, nr)
+    e, X, Y, it = riesz.riesz_window_solve(A, B, S, omega0, nr, nodes=8, tol=1e-11)
+    np.testing.assert_allclose(e, e_ref, rtol=0, atol=1e-11)
+    for k in range(nr):
+        ov = X[:, k] @ S @ X_ref[:, k] - Y[:, k] @ S @ Y_ref[:, k]
+        assert abs(abs(ov) - 1.0) < 1e-8, (k, ov)
+    assert it < 60
