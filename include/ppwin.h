@@ -59,6 +59,16 @@ typedef enum {
   PP_FP32 = 1        /* subspace products in FP32 matrix cores, FP64 residual refinement */
 } pp_precision;
 
+/* How a window solve isolates the roots near omega0 (pp_options.method). */
+typedef enum {
+  PP_FOLDED = 0,     /* inverse Krylov basis from weighted-Jacobi steps of the shifted pencil,
+                        folded-spectrum selection (the interior-eigenvalue subsection) */
+  PP_RIESZ = 1       /* Riesz projector (the section on its connection to the method): the
+                        block is filtered by trapezoidal quadrature of the contour integral of
+                        (z Sigma - M)^-1 Sigma on a circle around omega0, each shifted system
+                        solved by diagonal-preconditioned conjugate-orthogonal CG */
+} pp_method;
+
 /* pp_sigma flags */
 #define PP_APPLY_METRIC 1u  /* return Sigma X instead of M X */
 #define PP_DEVICE_PTRS 2u   /* X and out are device pointers */
@@ -84,7 +94,7 @@ typedef struct {
                                product; -1 (default): keep them when they fit the budget */
   int32_t strip_rows;       /* occupied rows per amplitude strip (0 = chosen from the budget) */
   double tol;               /* residual tolerance |(M - theta Sigma) y| / |y| (default 1e-9) */
-  int32_t block;            /* block size (0: n_roots + 2) */
+  int32_t block;            /* block size (0: n_roots + 2; 2 n_roots for PP_RIESZ) */
   int32_t krylov_steps;     /* basis vectors per cycle: corrections + (krylov_steps-1)
                                weighted-Jacobi steps (default 2) */
   int32_t max_basis;        /* largest subspace (default 480, at most 512) */
@@ -100,6 +110,14 @@ typedef struct {
                                F_k = <[q_k, mu]> over the MP2 ground state (Theory section,
                                the numerator of the propagator), which through second order is
                                the metric applied to mu: F = S mu (0: F = mu, zeroth order) */
+  int32_t method;           /* pp_method (default PP_FOLDED) */
+  int32_t contour_nodes;    /* PP_RIESZ: quadrature nodes on the upper half circle, 2n in all
+                               (default 6, at most 32); the filter on a root at x = (omega -
+                               omega0) / radius is 1 / (1 + x^(2n)) */
+  double contour_tol;       /* PP_RIESZ: relative residual at which the shifted solves of the
+                               first cycle stop (default 1e-4); later cycles stop at a tenth of
+                               the window's worst residual, down to tol / 10 */
+  int32_t contour_maxit;    /* PP_RIESZ: iteration cap of each shifted solve (default 500) */
 } pp_options;
 
 #define PP_MAX_ROOTS 64

@@ -63,6 +63,17 @@ pp_status ppint_cholesky(int32_t n, const double* A, double* L);
 pp_status ppint_products(pp_handle* h, int32_t order, int32_t k, const double* V, double* AV, double* BV,
                          double* SV, int32_t fp32);
 
+/* Riesz projector of the handle's pencil (section on the connection to the Riesz
+ * projector) applied to m vectors: out_j = (1/n) sum_{k<n} Re( r e^{i theta_k} x_k ),
+ * theta_k = pi (2k+1) / (2n), z_k = center + radius e^{i theta_k}, where x_k solves
+ * (z_k Sigma - M) x_k = Sigma V_j by diagonal-preconditioned conjugate-orthogonal CG to a
+ * relative residual tol (at most maxit iterations).  V, out: device [m][2][n_occ][n_vir]
+ * (X then Y of each vector); 1 <= m <= 64, 1 <= nodes <= 32.  *iters (nullable): largest
+ * iteration count; *worst (nullable): largest final relative residual.  PP_EINVAL for
+ * bad sizes, radius <= 0 or tol outside (0, 1). */
+pp_status ppint_riesz_filter(pp_handle* h, double center, double radius, int32_t nodes, double tol, int32_t maxit,
+                             int32_t m, const double* V, double* out, int32_t* iters, double* worst);
+
 #ifdef __cplusplus
 }
 #endif

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libppwin.so")
 
 PP_OK, PP_EINVAL, PP_ENOMEM, PP_ENOTCONV, PP_EUNSTABLE, PP_EDEVICE, PP_ENOTSUP, PP_EPENDING = range(8)
 PP_FP64, PP_FP32 = 0, 1
+PP_FOLDED, PP_RIESZ = 0, 1
 PP_APPLY_METRIC = 1
 PP_DEVICE_PTRS = 2
 PP_MAX_ROOTS = 64
@@ -40,7 +41,9 @@ class pp_options(C.Structure):
                 ("tol", C.c_double), ("block", C.c_int32), ("krylov_steps", C.c_int32),
                 ("max_basis", C.c_int32), ("max_cycles", C.c_int32), ("d_clamp", C.c_double),
                 ("hbm_budget", C.c_uint64), ("device", C.c_int32), ("stream", C.c_void_p),
-                ("seed", C.c_uint64), ("tda", C.c_int32), ("correlated_f", C.c_int32)]
+                ("seed", C.c_uint64), ("tda", C.c_int32), ("correlated_f", C.c_int32),
+                ("method", C.c_int32), ("contour_nodes", C.c_int32), ("contour_tol", C.c_double),
+                ("contour_maxit", C.c_int32)]
 
 
 class pp_solve_info(C.Structure):
@@ -132,6 +135,8 @@ def lib() -> C.CDLL:
         L.ppint_cholesky.restype = C.c_int
         L.ppint_products.argtypes = [vp, i32, i32, vp, vp, vp, vp, i32]
         L.ppint_products.restype = C.c_int
+        L.ppint_riesz_filter.argtypes = [vp, dbl, dbl, i32, dbl, i32, i32, vp, vp, C.POINTER(i32), C.POINTER(dbl)]
+        L.ppint_riesz_filter.restype = C.c_int
         L.pp_exciton_dos.argtypes = [vp, i32, vp, vp, vp]
         L.pp_exciton_dos.restype = C.c_int
         L.pp_spectrum.argtypes = [i32, vp, vp, i32, vp, dbl, vp]
@@ -253,6 +258,17 @@ class Handle:
                                   AV.data_ptr(), BV.data_ptr(), SV.data_ptr() if SV is not None else None,
                                   1 if fp32 else 0)
         _check(st, self.h)
+
+    def riesz_filter(self, V, out, center: float, radius: float, nodes: int, tol: float = 1e-10,
+                     maxit: int = 500):
+        """out = P V for torch device tensors [m][2][N] (contour quadrature of the resolvent;
+        internal test hook).  Returns (largest iteration count, largest final relative
+        residual) of the shifted solves."""
+        it, worst = C.c_int32(0), C.c_double(0.0)
+        st = lib().ppint_riesz_filter(self.h, float(center), float(radius), int(nodes), float(tol), int(maxit),
+                                      V.shape[0], V.data_ptr(), out.data_ptr(), C.byref(it), C.byref(worst))
+        _check(st, self.h)
+        return it.value, worst.value
 
     def window_solve(self, omega0: float, n_roots: int, vectors: bool = True, osc: bool = True,
                      allow_unconverged: bool = False):

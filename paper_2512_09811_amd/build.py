@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libppwin.so")
-SOURCES = ["gemm.hip", "kernels.hip", "dense_small.hip", "sigma.hip", "solver.hip", "capi.hip", "server.hip"]
+SOURCES = ["gemm.hip", "kernels.hip", "dense_small.hip", "sigma.hip", "riesz.hip", "solver.hip", "capi.hip", "server.hip"]
 ARCH = os.environ.get("PPWIN_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
          "-packed-fp32-ops", "-Wno-unused-command-line-argument"]

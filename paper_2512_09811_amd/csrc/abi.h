@@ -68,6 +68,12 @@ inline void check_options(const pp_options& opt) {
   if (opt.precision != PP_FP64 && opt.precision != PP_FP32) throw InvalidArg("unknown precision");
   if (opt.max_basis > 512) throw InvalidArg("max_basis must be <= 512");
   if (!(opt.tol > 0)) throw InvalidArg("tol must be positive");
+  if (opt.method != PP_FOLDED && opt.method != PP_RIESZ) throw InvalidArg("unknown method");
+  if (opt.method == PP_RIESZ) {
+    if (opt.contour_nodes < 1 || opt.contour_nodes > 32) throw InvalidArg("contour_nodes must be in 1..32");
+    if (!(opt.contour_tol > 0 && opt.contour_tol < 1)) throw InvalidArg("contour_tol must be in (0, 1)");
+    if (opt.contour_maxit < 1) throw InvalidArg("contour_maxit must be positive");
+  }
 }
 
 inline SolveOptions solve_options(const pp_options& o) {
@@ -81,6 +87,10 @@ inline SolveOptions solve_options(const pp_options& o) {
   so.d_clamp = o.d_clamp;
   so.seed = o.seed;
   so.correlated_f = o.correlated_f;
+  so.method = o.method;
+  so.contour_nodes = o.contour_nodes;
+  so.contour_tol = o.contour_tol;
+  so.contour_maxit = o.contour_maxit;
   return so;
 }
 

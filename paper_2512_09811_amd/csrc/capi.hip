@@ -9,6 +9,7 @@
 #include "../../include/ppwin_testing.h"
 #include "context.h"
 #include "kernels.h"
+#include "riesz.h"
 #include "solver.h"
 #include "abi.h"
 
@@ -43,6 +44,10 @@ void pp_default_options(pp_options* opt) {
   opt->device = 0;
   opt->stream = nullptr;
   opt->seed = 0;
+  opt->method = PP_FOLDED;
+  opt->contour_nodes = 6;
+  opt->contour_tol = 1e-4;
+  opt->contour_maxit = 500;
 }
 
 pp_status pp_setup(const pp_system* sys, const pp_options* opt_in, pp_handle** out) {
@@ -385,6 +390,50 @@ pp_status ppint_cholesky(int32_t n, const double* A, double* L) {
   return guarded(&err, [&] {
     ppw::small_cholesky(n, A, L, nullptr, nullptr);
     PPW_HIP(hipDeviceSynchronize());
+  });
+}
+
+pp_status ppint_riesz_filter(pp_handle* h, double center, double radius, int32_t nodes, double tol, int32_t maxit,
+                             int32_t m, const double* V, double* out, int32_t* iters, double* worst) {
+  if (!h || !h->ctx) return PP_EINVAL;
+  return guarded(&h->err, [&] {
+    ppw::Context& c = *h->ctx;
+    if (m < 1 || m > 64) throw ppw::InvalidArg("m must be in 1..64");
+    if (nodes < 1 || nodes > 32) throw ppw::InvalidArg("nodes must be in 1..32");
+    if (!(radius > 0) || !std::isfinite(center) || !(tol > 0 && tol < 1) || maxit < 1)
+      throw ppw::InvalidArg("bad contour parameters");
+    if (!V || !out) throw ppw::InvalidArg("NULL vector pointer");
+    PPW_HIP(hipSetDevice(c.device));
+    const long N = c.N;
+    double* W = c.arena.alloc<double>((size_t)2 * m * N, "riesz block");
+    struct Free {
+      ppw::Context& c;
+      double* p;
+      ~Free() { c.arena.free(p); }
+    } fr{c, W};
+    // [m][2][N] -> X rows then Y rows
+    PPW_HIP(hipMemcpy2DAsync(W, N * sizeof(double), V, 2 * N * sizeof(double), N * sizeof(double), m,
+                             hipMemcpyDeviceToDevice, c.stream));
+    PPW_HIP(hipMemcpy2DAsync(W + (size_t)m * N, N * sizeof(double), V + N, 2 * N * sizeof(double),
+                             N * sizeof(double), m, hipMemcpyDeviceToDevice, c.stream));
+    ppw::ContourFilter cf(c, m, nodes, 2 * m, c.stream);
+    ppw::ContourParams p;
+    p.center = center;
+    p.radius = radius;
+    p.nodes = nodes;
+    p.tol = tol;
+    p.maxit = maxit;
+    double wr = 0.0;
+    const int it = cf.apply(p, m, W, [&](int k, const double* X, double* AV, double* BV, double* SV) {
+      ppw::sigma_core(c, c.order, k, X, AV, BV, SV);
+    }, &wr);
+    PPW_HIP(hipMemcpy2DAsync(out, 2 * N * sizeof(double), W, N * sizeof(double), N * sizeof(double), m,
+                             hipMemcpyDeviceToDevice, c.stream));
+    PPW_HIP(hipMemcpy2DAsync(out + N, 2 * N * sizeof(double), W + (size_t)m * N, N * sizeof(double),
+                             N * sizeof(double), m, hipMemcpyDeviceToDevice, c.stream));
+    PPW_HIP(hipStreamSynchronize(c.stream));
+    if (iters) *iters = it;
+    if (worst) *worst = wr;
   });
 }
 

@@ -18,6 +18,10 @@ struct SolveOptions {
   double d_clamp = 1e-4;
   unsigned long long seed = 0;
   int correlated_f = 0;   // oscillator strengths from the property vector S mu (else mu)
+  int method = 0;         // 0 folded inverse Krylov, 1 Riesz projector (contour filter)
+  int contour_nodes = 6;  // Riesz: nodes on the upper half circle
+  double contour_tol = 1e-4;  // Riesz: first-cycle solve tolerance (later: adaptive)
+  int contour_maxit = 500;
 };
 
 // One window solve's request for A, B and S products of k orthonormal vectors V

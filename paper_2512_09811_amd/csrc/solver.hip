@@ -38,6 +38,7 @@
 #include <vector>
 
 #include "kernels.h"
+#include "riesz.h"
 #include "solver.h"
 
 namespace ppw {
@@ -372,6 +373,15 @@ __global__ void copy_cols_kernel(int rows, int cols, const double* __restrict__ 
 }
 
 // out[j] = sum_p (U[p][j]^2 + W[p][j]^2)
+// X = (u + w) / 2, Y = (u - w) / 2 for paired halves u = X + Y, w = X - Y ([k][N] each)
+__global__ void halves_kernel(long n, const double* __restrict__ U, const double* __restrict__ W,
+                              double* __restrict__ X, double* __restrict__ Y) {
+  GS_LOOP(i, n) {
+    X[i] = 0.5 * (U[i] + W[i]);
+    Y[i] = 0.5 * (U[i] - W[i]);
+  }
+}
+
 __global__ void coeff_norms_kernel(int rows, int cols, const double* __restrict__ U, const double* __restrict__ W,
                                    double* __restrict__ out) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -506,7 +516,9 @@ struct SolverDims {
 };
 SolverDims solver_dims(long N, int nroots, const SolveOptions& o) {
   SolverDims d;
-  d.m = o.block > 0 ? o.block : nroots + 2;
+  // the Riesz subspace iteration needs more vectors than roots (the filter separates the
+  // window from its neighbours through the block's extra vectors)
+  d.m = o.block > 0 ? o.block : (o.method == 1 ? 2 * nroots : nroots + 2);
   d.m = (int)std::min<long>(d.m, N);
   d.nbmax = (int)std::min<long>(o.max_basis > 0 ? o.max_basis : 480, N);
   d.nbmax = std::max(d.nbmax, std::min<int>((int)N, 2 * d.m));
@@ -528,9 +540,11 @@ class Solver {
     PPW_HIP(hipEventCreateWithFlags(&ev_ready_, hipEventDisableTiming));
     PPW_HIP(hipEventCreateWithFlags(&ev_done_, hipEventDisableTiming));
     alloc();
+    if (opt_.method == 1) cf_.reset(new ContourFilter(c_, m_, opt_.contour_nodes, kmax_, s_));
   }
   ~Solver() {
     if (s_) (void)hipStreamSynchronize(s_);
+    cf_.reset();
     for (void* p : owned_) c_.arena.free(p);
     if (ev_ready_) (void)hipEventDestroy(ev_ready_);
     if (ev_done_) (void)hipEventDestroy(ev_done_);
@@ -570,6 +584,11 @@ class Solver {
   int *keep_, *ival_, *sel_;
   double* noise_;
   long products_ = 0;
+  // Riesz projector mode: contour filter, circle radius around omega0, solve iterations
+  std::unique_ptr<ContourFilter> cf_;
+  double rad_ = 0.0;
+  long contour_iters_ = 0;
+  double contour_worst_ = 1.0;  // worst residual of the window when the block was formed
 
   template <typename T>
   T* get(size_t n, const char* w) {
@@ -688,16 +707,17 @@ class Solver {
 
   // A, B, S products of k orthonormal vectors X (device, [k][N]) into AV_, BV_, SV_,
   // merged with the other windows' requests by the batcher
-  void products(int k, const double* X, bool exact) {
+  void products(int k, const double* X, bool exact) { products_into(k, X, AV_, BV_, SV_, exact); }
+  void products_into(int k, const double* X, double* AV, double* BV, double* SV, bool exact) {
     ProductRequest r;
     r.id = id_;
     r.ctx = &c_;
     r.k = k;
     r.prec = (exact || opt_.precision != 1 || refined_) ? 0 : 1;
     r.V = X;
-    r.AV = AV_;
-    r.BV = BV_;
-    r.SV = SV_;
+    r.AV = AV;
+    r.BV = BV;
+    r.SV = SV;
     r.ready = ev_ready_;
     r.done = ev_done_;
     PPW_HIP(hipEventRecord(ev_ready_, s_));
@@ -887,6 +907,39 @@ class Solver {
     return out;
   }
 
+  // Riesz projector mode: V_ (X rows [0, k), Y rows [k, 2k)) <- P V_ on the circle of
+  // radius rad_ around omega0
+  void contour_step(int k) {
+    ContourParams p;
+    p.center = w0_;
+    p.radius = rad_;
+    p.nodes = opt_.contour_nodes;
+    // shifted solves: contour_tol on the first cycle, then a tenth of the window's worst
+    // residual (the filtered subspace is only as accurate as the solves), down to a
+    // tenth of the solver tolerance (FP32 products: not below 1e-6)
+    const double floor_tol = (opt_.precision == 1 && !refined_) ? 1e-6 : 0.1 * opt_.tol;
+    p.tol = std::max(floor_tol, std::min(opt_.contour_tol, 0.1 * contour_worst_));
+    p.maxit = opt_.contour_maxit;
+    double worst = 0.0;
+    const int it = cf_->apply(p, k, V_, [this](int kc, const double* X, double* AV, double* BV, double* SV) {
+      products_into(kc, X, AV, BV, SV, false);
+    }, &worst);
+    contour_iters_ += it;
+    if (trace_)
+      std::fprintf(stderr, "[ppwin] window %d contour radius %.3e: %d vectors, %d iterations, residual %.2e\n", id_,
+                   rad_, k, it, worst);
+  }
+  // V_ <- X and Y halves of the Ritz vectors listed in act (from the current basis)
+  void ritz_block(const std::vector<int>& act) {
+    const int k = (int)act.size(), n = nb_;
+    upload(sel_, act);
+    gather_cols_kernel<<<gridn((long)n * k), kB, 0, s_>>>(n, k, sel_, us_, rld_, c1_, k, 0);
+    gather_cols_kernel<<<gridn((long)n * k), kB, 0, s_>>>(n, k, sel_, ws_, rld_, c2_, k, 0);
+    expand(k, n, c1_, k, Q_, T1_);
+    expand(k, n, c2_, k, Q_, T2_);
+    halves_kernel<<<gridn(N_ * k), kB, 0, s_>>>(N_ * k, T1_, T2_, V_, V_ + (size_t)k * N_);
+  }
+
   struct Ritz {
     std::vector<double> th, rn, fold;
   };
@@ -989,6 +1042,13 @@ void Solver::run(double* energies, double* vectors, double* osc, pp_solve_info* 
   upload(noise_, noise);
   upload(sel_, pos);
   start_block_kernel<<<gridn(N_ * m_), kB, 0, s_>>>(N_, m_, sel_, noise_, V_, V_ + (size_t)m_ * N_);
+  if (cf_) {
+    // first circle from the zeroth-order picture: the diagonal estimates A_ii / S_ii
+    std::vector<double> d(N_);
+    for (long i = 0; i < N_; ++i) d[i] = std::fabs(dA[i] / dS[i] - w0_);
+    std::sort(d.begin(), d.end());
+    rad_ = 1.5 * d[std::min<long>(nr_, N_) - 1] + 1e-6;
+  }
 
   int knew = m_;  // columns in the new block (X in V_[0..k), Y in V_[k..2k))
   Ritz R;
@@ -1002,7 +1062,12 @@ void Solver::run(double* energies, double* vectors, double* osc, pp_solve_info* 
   double best_worst = 1e300;
   int since_best = 0;
   for (cycle = 0; cycle < opt_.max_cycles; ++cycle) {
-   if (knew > 0) {
+   if (knew > 0 && cf_) {
+    // Riesz projector mode (subspace iteration): the filtered block replaces the subspace
+    contour_step(knew);
+    nb_ = 0;
+    extend(V_, 2 * knew);
+   } else if (knew > 0) {
     // X, Y halves are contiguous in V_: [X_0..X_k-1, Y_0..Y_k-1]
     const int kk = 2 * knew;
     extend(V_, kk);
@@ -1103,6 +1168,15 @@ void Solver::run(double* energies, double* vectors, double* osc, pp_solve_info* 
     // some inner pair is unresolved)
     if ((int)inner.size() >= nr_) out.assign(inner.begin(), inner.begin() + nr_);
     else out = tgt;
+    if (cf_) {
+      // the circle passes halfway between the window's farthest Ritz value and the next
+      std::vector<double> dist(n);
+      for (int j = 0; j < n; ++j) dist[j] = std::fabs(R.th[j] - w0_);
+      std::sort(dist.begin(), dist.end());
+      if (n > nr_) rad_ = 0.5 * (dist[nr_ - 1] + dist[nr_]);
+      else if (n > 0) rad_ = 1.25 * dist[n - 1];
+      rad_ = std::max(rad_, 1e-8);
+    }
     if (worst < 0.5 * best_worst) {
       best_worst = worst;
       since_best = 0;
@@ -1162,9 +1236,17 @@ void Solver::run(double* energies, double* vectors, double* osc, pp_solve_info* 
     knew = (int)act.size();
     upload(sel_, act);
     // corrections into V_ (X part then Y part); residual vectors are in RU_/RW_
-    correction_kernel<<<gridn(N_ * knew), kB, 0, s_>>>(N_, knew, sel_, th_, clampv, c_.dA, c_.dB, c_.dS, RU_, RW_, V_,
-                                                        V_ + (size_t)knew * N_);
-    if (nb_ + 2 * opt_.krylov_steps * knew > nbmax_) restart(blk);
+    if (cf_) {
+      // Riesz mode: the next block is the block's Ritz vectors, filtered at the start of
+      // the next cycle; solves are tightened as the window converges
+      knew = (int)blk.size();
+      ritz_block(blk);
+      contour_worst_ = worst;
+    } else {
+      correction_kernel<<<gridn(N_ * knew), kB, 0, s_>>>(N_, knew, sel_, th_, clampv, c_.dA, c_.dB, c_.dS, RU_, RW_,
+                                                          V_, V_ + (size_t)knew * N_);
+      if (nb_ + 2 * opt_.krylov_steps * knew > nbmax_) restart(blk);
+    }
   }
   // outputs: the window's roots, ascending energy
   std::vector<int> sel = out;
@@ -1308,6 +1390,7 @@ size_t window_solve_bytes(long N, int n_roots, const SolveOptions& opt) {
   t += 2 * r(std::max(d.kmax, d.nbmax) * sizeof(int)) + r(4 * sizeof(int));
   t += r((size_t)2 * d.m * N * D);                      // noise
   t += r((size_t)32 << 20);                             // split-K workspace
+  if (opt.method == 1) t += ContourFilter::bytes(N, d.m, opt.contour_nodes);
   return t;
 }
 
