@@ -78,6 +78,9 @@ def parse():
     ap.add_argument("--occ", default="16,40", help="serving: n_occ range lo,hi (the full stream is 16,128)")
     ap.add_argument("--no-plain-compare", action="store_true",
                     help="serving: skip solving the timed requests one by one on plain FP64 handles")
+    ap.add_argument("--riesz", action="store_true",
+                    help="Riesz-projector windows against folded inverse-Krylov windows on the same small and "
+                         "mid-size systems (its own JSON line)")
     return ap.parse_args()
 
 
@@ -105,6 +108,54 @@ def cpu_baseline(name):
     return dict(value=len(omegas) / dt, unit="solves/s", cores=int(cores), kind="oracle",
                 sample=f"dense oracle on the full workload: assembly of A, B, S (N = {sys_.N}) and exact pencil "
                        f"diagonalisation, one diagonalisation serving all {len(omegas)} windows; {dt:.1f} s")
+
+
+# Riesz-projector comparison: (name, n_occ, n_vir, n_aux, order, seed, windows, roots)
+RIESZ_WORKLOADS = [("rpa1_o8_v24_x64", 8, 24, 64, 1, 1, [0.5], 6),
+                   ("mp2_o16_v64_x192", 16, 64, 192, 2, 6, [0.4, 0.8], 8)]
+
+
+def riesz_main(args):
+    """Window solves by the Riesz projector (contour-filtered subspace iteration) and by
+    the folded inverse-Krylov method on the same systems, each window checked against
+    the oracle; solves/s over the timed repetitions of each batch of windows."""
+    import torch  # noqa: F401  (initializes the device runtime first)
+    import paper_2512_09811_amd as P
+    from synth.gen import gen
+    from oracle import dense, pencil
+    results = []
+    for name, o, v, naux, order, seed, oms, nr in RIESZ_WORKLOADS:
+        sys_ = gen(seed, o, v, naux)
+        A, B, S = dense.assemble(sys_, order)
+        ref = [pencil.window_solve(A, B, S, sys_.dip, w, nr) for w in oms]
+        for method in ("folded", "riesz"):
+            m = P.PP_RIESZ if method == "riesz" else P.PP_FOLDED
+            with P.Handle.from_system(sys_, order=order, method=m, tol=args.tol) as h:
+                h.window_solve_batch(oms, nr)                       # warm-up
+                t0 = time.perf_counter()
+                for _ in range(max(1, args.steps)):
+                    E, V, F, infos = h.window_solve_batch(oms, nr)
+                dt = (time.perf_counter() - t0) / max(1, args.steps)
+            de = max(float(np.abs(E[w] - ref[w][0]).max()) for w in range(len(oms)))
+            df = 0.0
+            ok = 0
+            for w in range(len(oms)):
+                fr = ref[w][3]
+                big = fr >= 1e-4 * fr.max()
+                rel = float(np.max(np.abs(F[w][big] - fr[big]) / fr[big])) if big.any() else 0.0
+                df = max(df, rel)
+                ok += int(np.abs(E[w] - ref[w][0]).max() <= 1e-6 and rel <= 1e-5)
+            results.append(dict(workload=name, method=method, value=ok / dt, unit="solves/s",
+                                seconds_per_batch=dt, windows=len(oms), n_roots=nr,
+                                windows_meeting_tolerance=f"{ok}/{len(oms)}",
+                                products_per_window=float(np.mean([i["products"] for i in infos])),
+                                cycles_per_window=float(np.mean([i["cycles"] for i in infos])),
+                                max_abs_dE_ha=de, max_rel_df=df))
+            print(f"[riesz] {name} {method}: {ok / dt:.2f} solves/s, "
+                  f"{results[-1]['products_per_window']:.0f} products/window", file=sys.stderr, flush=True)
+    print(json.dumps(dict(metric="window solves/s, Riesz projector vs folded inverse Krylov", unit="solves/s",
+                          dtype="f64", data="synthetic (seeded generator)", solver_tol=args.tol,
+                          results=results)), flush=True)
 
 
 def serve_main(args):
@@ -224,6 +275,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is a design "
                                    "note, not implemented)"}))
         sys.exit(2)
+    if args.riesz:
+        riesz_main(args)
+        return
     if args.serve:
         serve_main(args)
         return
