@@ -354,11 +354,35 @@ __global__ __launch_bounds__(kT) void trinv_kernel(int n, const double* __restri
 
 // Householder tridiagonalization (one workgroup).  d[n], e[n] (e[i] couples i, i+1);
 // Hh[k][n] holds the unit reflector u_k of step k (zero in entries <= k).
+//
+// Step k reflects column k of the trailing block B (rows and columns k+1..n-1):
+// u from that column, q = B u - (u.B u) u, then B -= 2 (u q^T + q u^T).  The kernel is
+// bound by the bandwidth between the L2 and its one CU, so the rank-2 update of step k
+// and the product B' u' of step k+1 share one sweep over the block: column k+1 of the
+// updated block (which defines u') is formed first from the update formula, then every
+// updated element of rows and columns k+2.. is written back and multiplied into B' u'
+// in the same pass (one read and one write per element per step instead of two reads
+// and one write).
+__device__ __forceinline__ void reflector(int m, const double* __restrict__ col, double* __restrict__ u,
+                                          double* red, double& alpha, bool& nonzero) {
+  // u = (col - alpha e_0) / |col - alpha e_0| with alpha = -sign(col_0) |col|
+  double part = 0.0;
+  for (int r = threadIdx.x; r < m; r += blockDim.x) part += col[r] * col[r];
+  const double xx = block_reduce_sum(part, red);
+  const double x0 = col[0];
+  const double xnorm = sqrt(xx);
+  nonzero = xnorm != 0.0;
+  alpha = x0 > 0 ? -xnorm : xnorm;
+  if (!nonzero) return;
+  const double vnorm = sqrt(2.0 * xx - 2.0 * x0 * alpha);
+  for (int r = threadIdx.x; r < m; r += blockDim.x) u[r] = (r == 0 ? col[r] - alpha : col[r]) / vnorm;
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(kT) void tridiag_kernel(int n, const double* __restrict__ A, double* __restrict__ W,
                                                      double* __restrict__ dout, double* __restrict__ eout,
                                                      double* __restrict__ Hh) {
-  __shared__ double u[kMaxN];
-  __shared__ double q[kMaxN];
+  __shared__ double u[kMaxN], q[kMaxN], un[kMaxN], qn[kMaxN], col[kMaxN];
   __shared__ double red[40];
   const int tid = threadIdx.x;
   const long nn = (long)n * n;
@@ -367,48 +391,96 @@ __global__ __launch_bounds__(kT) void tridiag_kernel(int n, const double* __rest
     Hh[i] = 0.0;
   }
   __syncthreads();
-  for (int k = 0; k + 2 < n; ++k) {
-    const int m = n - k - 1;
-    double part = 0.0;
-    for (int r = tid; r < m; r += kT) {
-      const double x = W[(long)(k + 1 + r) * n + k];
-      part += x * x;
-    }
-    const double xx = block_reduce_sum(part, red);
-    const double x0 = W[(long)(k + 1) * n + k];
-    const double xnorm = sqrt(xx);
-    if (tid == 0) dout[k] = W[(long)k * n + k];
-    if (xnorm == 0.0) {
-      if (tid == 0) eout[k] = 0.0;
-      __syncthreads();
-      continue;
-    }
-    const double alpha = x0 > 0 ? -xnorm : xnorm;
-    const double vnorm = sqrt(2.0 * xx - 2.0 * x0 * alpha);
-    for (int r = tid; r < m; r += kT) {
-      const double x = W[(long)(k + 1 + r) * n + k];
-      u[r] = (r == 0 ? x - alpha : x) / vnorm;
-    }
-    __syncthreads();
+  // q = B u for the block of step k (rows/columns k+1..k+m), u in LDS
+  auto symv = [&](int k, int m) {
     for (int r = tid; r < m; r += kT) {
       double acc = 0.0;
       for (int cc = 0; cc < m; ++cc) acc += W[(long)(k + 1 + cc) * n + (k + 1 + r)] * u[cc];
       q[r] = acc;
     }
     __syncthreads();
+  };
+  // reflector and product of step k from the stored column k (no pending update)
+  bool refl = false;
+  double alpha = 0.0;
+  auto start_step = [&](int k) {
+    const int m = n - k - 1;
+    for (int r = tid; r < m; r += kT) col[r] = W[(long)(k + 1 + r) * n + k];
+    __syncthreads();
+    reflector(m, col, u, red, alpha, refl);
+    if (refl) symv(k, m);
+  };
+  if (n >= 3) start_step(0);
+  for (int k = 0; k + 2 < n; ++k) {
+    const int m = n - k - 1;
+    if (tid == 0) dout[k] = W[(long)k * n + k];
+    if (!refl) {
+      // column k is already reduced: nothing to apply
+      if (tid == 0) eout[k] = 0.0;
+      __syncthreads();
+      if (k + 3 < n) start_step(k + 1);
+      continue;
+    }
     double kp = 0.0;
     for (int r = tid; r < m; r += kT) kp += u[r] * q[r];
     const double K = block_reduce_sum(kp, red);
-    for (int r = tid; r < m; r += kT) q[r] = q[r] - K * u[r];
-    __syncthreads();
-    const long mm = (long)m * m;
-    for (long idx = tid; idx < mm; idx += kT) {
-      const int r = (int)(idx / m), cc = (int)(idx % m);
-      W[(long)(k + 1 + r) * n + (k + 1 + cc)] -= 2.0 * (u[r] * q[cc] + q[r] * u[cc]);
+    for (int r = tid; r < m; r += kT) {
+      q[r] = q[r] - K * u[r];
+      Hh[(long)k * n + k + 1 + r] = u[r];
     }
-    for (int r = tid; r < m; r += kT) Hh[(long)k * n + k + 1 + r] = u[r];
     if (tid == 0) eout[k] = alpha;
     __syncthreads();
+    if (k + 3 < n) {
+      // column k+1 of the updated block (rows k+2..) and its diagonal element
+      for (int r = tid + 1; r < m; r += kT)
+        col[r - 1] = W[(long)(k + 1 + r) * n + (k + 1)] - 2.0 * (u[r] * q[0] + q[r] * u[0]);
+      if (tid == 0) W[(long)(k + 1) * n + (k + 1)] -= 2.0 * (u[0] * q[0] + q[0] * u[0]);
+      __syncthreads();
+      bool nref = false;
+      double nalpha = 0.0;
+      reflector(m - 1, col, un, red, nalpha, nref);
+      // fused sweep over rows/columns k+2..n-1: update, and accumulate B' u'
+      for (int c = tid + 1; c < m; c += kT) {
+        const double qc = q[c], uc = u[c];
+        double* Wc = W + (long)(k + 1) * n + (k + 1 + c);  // element (row r, this column) at Wc[r * n]
+        double acc = 0.0;
+        int r = 1;
+        // eight rows per batch: the loads are issued before any store of the batch, so
+        // they are in flight together (a store to W could otherwise alias a later load)
+        for (; r + 8 <= m; r += 8) {
+          double w[8];
+#pragma unroll
+          for (int t = 0; t < 8; ++t) w[t] = Wc[(long)(r + t) * n];
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            w[t] = w[t] - 2.0 * (u[r + t] * qc + q[r + t] * uc);
+            Wc[(long)(r + t) * n] = w[t];
+            if (nref) acc += w[t] * un[r + t - 1];
+          }
+        }
+        for (; r < m; ++r) {
+          const double w = Wc[(long)r * n] - 2.0 * (u[r] * qc + q[r] * uc);
+          Wc[(long)r * n] = w;
+          if (nref) acc += w * un[r - 1];
+        }
+        qn[c - 1] = acc;
+      }
+      __syncthreads();
+      for (int r = tid; r < m - 1; r += kT) {
+        u[r] = un[r];
+        q[r] = qn[r];
+      }
+      refl = nref;
+      alpha = nalpha;
+      __syncthreads();
+    } else {
+      const long mm = (long)m * m;
+      for (long idx = tid; idx < mm; idx += kT) {
+        const int r = (int)(idx / m), cc = (int)(idx % m);
+        W[(long)(k + 1 + r) * n + (k + 1 + cc)] -= 2.0 * (u[r] * q[cc] + q[r] * u[cc]);
+      }
+      __syncthreads();
+    }
   }
   if (tid == 0) {
     if (n >= 2) {

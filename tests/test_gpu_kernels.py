@@ -83,7 +83,7 @@ def test_gemm_layouts(B, fp32, pads, M, N, K, KB, nb, tA, tB):
         np.testing.assert_allclose(got, exp, rtol=(2e-5 if fp32 else 0), atol=tol)
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 5, 37, 64, 65, 130, 400])
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 24, 34, 37, 64, 65, 130, 400])
 def test_small_syev(B, n):
     rng = np.random.default_rng(n)
     X = rng.standard_normal((n, n))
@@ -99,6 +99,32 @@ def test_small_syev(B, n):
     w, Z = w.cpu().numpy(), Z.cpu().numpy()
     np.testing.assert_allclose(w, w_ref, rtol=0, atol=1e-12 * max(1.0, np.abs(w_ref).max()))
     assert np.abs(A @ Z - Z * w).max() < 1e-11 * max(1.0, np.abs(w_ref).max())
+    assert np.abs(Z.T @ Z - np.eye(n)).max() < 1e-12
+
+
+@pytest.mark.parametrize("n,kind", [(6, "identity"), (30, "repeated"), (48, "clustered"), (64, "diagonal")])
+def test_small_syev_degenerate(B, n, kind):
+    """Small eigenproblems with repeated, clustered or already diagonal spectra (the Gram
+    matrices of nearly dependent vectors the solver orthonormalises)."""
+    rng = np.random.default_rng(n)
+    if kind == "identity":
+        lam = np.ones(n)
+    elif kind == "repeated":
+        lam = np.repeat([0.5, 1.0, 2.0], n // 3)
+    elif kind == "clustered":
+        lam = np.concatenate([1.0 + 1e-13 * rng.standard_normal(n // 2), rng.uniform(1e-14, 3.0, n - n // 2)])
+    else:
+        lam = rng.uniform(-1.0, 1.0, n)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    A = np.diag(lam) if kind == "diagonal" else (Q * lam) @ Q.T
+    A = 0.5 * (A + A.T)
+    dA = torch.tensor(A, dtype=torch.float64, device="cuda")
+    w = torch.empty(n, dtype=torch.float64, device="cuda")
+    Z = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    B.syev(dA, w, Z)
+    w, Z = w.cpu().numpy(), Z.cpu().numpy()
+    np.testing.assert_allclose(w, np.sort(lam), rtol=0, atol=1e-13 * max(1.0, np.abs(lam).max()))
+    assert np.abs(A @ Z - Z * w).max() < 1e-12 * max(1.0, np.abs(lam).max())
     assert np.abs(Z.T @ Z - np.eye(n)).max() < 1e-12
 
 
@@ -149,7 +175,8 @@ def _spectrum_matrix(lam, seed):
     return (Q * lam) @ Q.T
 
 
-@pytest.mark.parametrize("case", ["uniform", "dense_near_target", "near_degenerate", "edge_target", "small"])
+@pytest.mark.parametrize("case", ["uniform", "dense_near_target", "near_degenerate", "edge_target", "small",
+                                  "diagonal", "block_diagonal"])
 def test_partial_syev(B, case):
     """The p eigenpairs nearest a target (projected problem of the window solver)."""
     rng = np.random.default_rng(5)
@@ -166,10 +193,20 @@ def test_partial_syev(B, case):
     elif case == "edge_target":
         target = 0.05
         lam = rng.uniform(0.1, 3.0, n)
+    elif case in ("diagonal", "block_diagonal"):
+        lam = rng.uniform(0.1, 3.0, n)
     else:
         n, p = 30, 12
         lam = rng.uniform(0.5, 1.5, n)
     A = _spectrum_matrix(lam, 11)
+    if case == "diagonal":
+        # every Householder column is already zero below the subdiagonal
+        A = np.diag(lam)
+    elif case == "block_diagonal":
+        # zero columns (first 150 rows/columns diagonal) then a dense block
+        A = np.zeros((n, n))
+        A[:150, :150] = np.diag(lam[:150])
+        A[150:, 150:] = _spectrum_matrix(lam[150:], 12)
     dA = torch.tensor(A, device="cuda")
     lam_d = torch.zeros(p, dtype=torch.float64, device="cuda")
     Z = torch.zeros(n * p, dtype=torch.float64, device="cuda")
