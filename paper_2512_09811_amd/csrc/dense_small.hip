@@ -288,7 +288,7 @@ __global__ __launch_bounds__(kT) void cholesky_kernel(int n, const double* __res
 // factor, in place in W (row-major n x n; only the lower triangle is read); the
 // update of the trailing columns is a GEMM issued by the host.  info (nullable):
 // 0 on success, j+1 for the first non-positive pivot j (later panels then stop).
-__global__ __launch_bounds__(256) void chol_panel_kernel(int n, int j0, int jb, double* __restrict__ W,
+__global__ __launch_bounds__(1024) void chol_panel_kernel(int n, int j0, int jb, double* __restrict__ W,
                                                          int* __restrict__ info) {
   __shared__ double piv;
   __shared__ int bad;
@@ -299,6 +299,7 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(int n, int j0, int jb, 
   }
   __syncthreads();
   if (bad) return;
+  __shared__ double colj[64];  // column j of the panel rows j+1..kend-1 (jb <= 64)
   const int kend = j0 + jb;
   for (int j = j0; j < kend; ++j) {
     if (tid == 0) {
@@ -314,15 +315,36 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(int n, int j0, int jb, 
     __syncthreads();
     if (bad) return;
     const double l = piv;
-    for (int i = j + 1 + tid; i < n; i += blockDim.x) W[(long)i * n + j] /= l;
+    for (int i = j + 1 + tid; i < n; i += blockDim.x) {
+      const double x = W[(long)i * n + j] / l;
+      W[(long)i * n + j] = x;
+      if (i < kend) colj[i - j - 1] = x;
+    }
     __syncthreads();
-    // rest of the panel: W[i][k] -= W[i][j] W[k][j] for j < k < kend, k <= i
-    const int nk = kend - (j + 1);
-    if (nk > 0) {
-      const long cnt = (long)(n - (j + 1)) * nk;
-      for (long idx = tid; idx < cnt; idx += blockDim.x) {
-        const int i = j + 1 + (int)(idx / nk), k = j + 1 + (int)(idx % nk);
-        if (k <= i) W[(long)i * n + k] -= W[(long)i * n + j] * W[(long)k * n + j];
+    // rest of the panel: W[i][k] -= W[i][j] W[k][j] for j < k < kend, k <= i; a wave
+    // takes one row at a time (lane = column k), the waves interleave rows
+    {
+      const int lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+      const int k = j + 1 + lane;
+      if (k < kend) {
+        const double lkj = colj[lane];
+        // eight rows per batch, all loads issued before the stores
+        for (int i0 = j + 1 + wv; i0 < n; i0 += 8 * nw) {
+          double a[8], b[8];
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            const int i = i0 + nw * t;
+            if (i < n) {
+              a[t] = W[(long)i * n + j];
+              b[t] = W[(long)i * n + k];
+            }
+          }
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            const int i = i0 + nw * t;
+            if (i < n && k <= i) W[(long)i * n + k] = b[t] - a[t] * lkj;
+          }
+        }
       }
     }
     __syncthreads();
@@ -506,6 +528,82 @@ __device__ int sturm_count(int n, const double* d, const double* e, double x, do
   return c;
 }
 
+// Eigenvector of the tridiagonal (sd, se) for the eigenvalue lmb by inverse iteration:
+// partially pivoted LU of T - lmb I (a zero pivot is replaced by pert), then four solves
+// from a fixed start vector, each normalised.  The work arrays are private to the
+// calling thread and do not overlap (restrict), so their loads can be issued ahead of
+// the dependent recurrences.
+__device__ void inverse_iteration(int n, const double* sd, const double* se, double lmb, double pert, int seed,
+                                  double* __restrict__ dl, double* __restrict__ dd, double* __restrict__ du,
+                                  double* __restrict__ du2, double* __restrict__ x, int* __restrict__ piv,
+                                  double* __restrict__ out) {
+  for (int i = 0; i < n; ++i) {
+    dd[i] = sd[i] - lmb;
+    if (i + 1 < n) {
+      dl[i] = se[i];
+      du[i] = se[i];
+    }
+    du2[i] = 0.0;
+    piv[i] = i;
+  }
+  for (int i = 0; i + 1 < n; ++i) {
+    if (fabs(dd[i]) >= fabs(dl[i])) {
+      if (dd[i] == 0.0) dd[i] = pert;
+      const double f = dl[i] / dd[i];
+      dl[i] = f;
+      dd[i + 1] -= f * du[i];
+    } else {
+      const double f = dd[i] / dl[i];
+      dd[i] = dl[i];
+      dl[i] = f;
+      const double tmp = du[i];
+      du[i] = dd[i + 1];
+      dd[i + 1] = tmp - f * dd[i + 1];
+      if (i + 2 < n) {
+        du2[i] = du[i + 1];
+        du[i + 1] = -f * du[i + 1];
+      }
+      piv[i] = i + 1;
+    }
+  }
+  if (dd[n - 1] == 0.0) dd[n - 1] = pert;
+  // deterministic start vector
+  for (int i = 0; i < n; ++i) x[i] = 1.0 + 0.5 * sin(0.7 * i + 1.3 * seed + 0.1);
+  for (int iter = 0; iter < 4; ++iter) {
+    double xi = x[0];
+    for (int i = 0; i + 1 < n; ++i) {
+      const double xn = x[i + 1];
+      if (piv[i] == i) {
+        x[i] = xi;
+        xi = xn - dl[i] * xi;
+      } else {
+        x[i] = xn;
+        xi = xi - dl[i] * xn;
+      }
+    }
+    x[n - 1] = xi;
+    double x1 = x[n - 1] / dd[n - 1];
+    x[n - 1] = x1;
+    double x2 = 0.0;
+    if (n >= 2) {
+      x2 = x1;
+      x1 = (x[n - 2] - du[n - 2] * x2) / dd[n - 2];
+      x[n - 2] = x1;
+    }
+    for (int i = n - 3; i >= 0; --i) {
+      const double xi0 = (x[i] - du[i] * x1 - du2[i] * x2) / dd[i];
+      x[i] = xi0;
+      x2 = x1;
+      x1 = xi0;
+    }
+    double s2 = 0.0;
+    for (int i = 0; i < n; ++i) s2 += x[i] * x[i];
+    const double inv = 1.0 / sqrt(s2);
+    for (int i = 0; i < n; ++i) x[i] *= inv;
+  }
+  for (int i = 0; i < n; ++i) out[i] = x[i];
+}
+
 // The p eigenvalues of the tridiagonal nearest 'target': the p below and the p above
 // it by bisection (one per thread), the p nearest of those, then their vectors by
 // inverse iteration with partially pivoted LU.  V[t][n]: vector t; lam[t] ascending;
@@ -575,65 +673,9 @@ __global__ __launch_bounds__(kT) void slice_kernel(int n, const double* __restri
   if (tid < p) {
     const double lmb = cand[pick[tid]];
     lam[tid] = lmb;
-    // inverse iteration on (T - lmb I)
-    double* dl = work + (long)tid * 6 * n;
-    double* dd = dl + n;
-    double* du = dd + n;
-    double* du2 = du + n;
-    double* x = du2 + n;
-    int* piv = (int*)(x + n);  // n ints fit in n doubles
-    const double pert = 1e-15 * fmax(scale, 1e-300);
-    for (int i = 0; i < n; ++i) {
-      dd[i] = sd[i] - lmb;
-      if (i + 1 < n) {
-        dl[i] = se[i];
-        du[i] = se[i];
-      }
-      du2[i] = 0.0;
-      piv[i] = i;
-    }
-    for (int i = 0; i + 1 < n; ++i) {
-      if (fabs(dd[i]) >= fabs(dl[i])) {
-        if (dd[i] == 0.0) dd[i] = pert;
-        const double f = dl[i] / dd[i];
-        dl[i] = f;
-        dd[i + 1] -= f * du[i];
-      } else {
-        const double f = dd[i] / dl[i];
-        dd[i] = dl[i];
-        dl[i] = f;
-        const double tmp = du[i];
-        du[i] = dd[i + 1];
-        dd[i + 1] = tmp - f * dd[i + 1];
-        if (i + 2 < n) {
-          du2[i] = du[i + 1];
-          du[i + 1] = -f * du[i + 1];
-        }
-        piv[i] = i + 1;
-      }
-    }
-    if (dd[n - 1] == 0.0) dd[n - 1] = pert;
-    // deterministic start vector
-    for (int i = 0; i < n; ++i) x[i] = 1.0 + 0.5 * sin(0.7 * i + 1.3 * tid + 0.1);
-    for (int iter = 0; iter < 4; ++iter) {
-      for (int i = 0; i + 1 < n; ++i) {
-        if (piv[i] == i) {
-          x[i + 1] -= dl[i] * x[i];
-        } else {
-          const double t = x[i];
-          x[i] = x[i + 1];
-          x[i + 1] = t - dl[i] * x[i];
-        }
-      }
-      x[n - 1] /= dd[n - 1];
-      if (n >= 2) x[n - 2] = (x[n - 2] - du[n - 2] * x[n - 1]) / dd[n - 2];
-      for (int i = n - 3; i >= 0; --i) x[i] = (x[i] - du[i] * x[i + 1] - du2[i] * x[i + 2]) / dd[i];
-      double s2 = 0.0;
-      for (int i = 0; i < n; ++i) s2 += x[i] * x[i];
-      const double inv = 1.0 / sqrt(s2);
-      for (int i = 0; i < n; ++i) x[i] *= inv;
-    }
-    for (int i = 0; i < n; ++i) V[(long)tid * n + i] = x[i];
+    double* base = work + (long)tid * 6 * n;
+    inverse_iteration(n, sd, se, lmb, 1e-15 * fmax(scale, 1e-300), tid, base, base + n, base + 2 * n, base + 3 * n,
+                      base + 4 * n, (int*)(base + 5 * n), V + (long)tid * n);
   }
 }
 
@@ -813,7 +855,7 @@ void small_cholesky(int n, const double* A, double* L, int* info, hipStream_t s)
   PPW_HIP(hipMemcpyAsync(L, A, sizeof(double) * n * n, hipMemcpyDeviceToDevice, s));
   for (int j0 = 0; j0 < n; j0 += NB) {
     const int jb = std::min(NB, n - j0);
-    chol_panel_kernel<<<1, 256, 0, s>>>(n, j0, jb, L, info);
+    chol_panel_kernel<<<1, 1024, 0, s>>>(n, j0, jb, L, info);
     PPW_LAUNCH_CHECK();
     const int j1 = j0 + jb, m2 = n - j1;
     if (m2 > 0) {
