@@ -40,11 +40,18 @@ __device__ double block_reduce_sum(double v, double* red) {
 
 // W: n x n working copy (row-major, symmetric), Zc: n x n, column-major eigenvectors.
 // NT threads (1024 for the large projected problems; one wave for n <= 64, where the
-// block-wide barriers of the rotation sweeps cost more than the arithmetic).
-template <int NT>
+// block-wide barriers of the rotation sweeps cost more than the arithmetic).  INLDS
+// (n <= 64): W and Zr live in LDS instead of the scratch arrays passed in, so the
+// sweeps run at LDS latency rather than at that of an L2 shared with concurrent GEMMs.
+template <int NT, bool INLDS>
 __global__ __launch_bounds__(NT) void syev_kernel(int n, const double* __restrict__ A, double* __restrict__ w,
                                                   double* __restrict__ Z, double* __restrict__ W,
                                                   double* __restrict__ Zr) {
+  __shared__ double lds_w[INLDS ? 64 * 64 : 1], lds_z[INLDS ? 64 * 64 : 1];
+  if (INLDS) {
+    W = lds_w;
+    Zr = lds_z;
+  }
   __shared__ double u[kMaxN];
   __shared__ double q[kMaxN];
   __shared__ double d[kMaxN];
@@ -763,9 +770,9 @@ void small_syev(int n, const double* A, double* w, double* Z, hipStream_t s, dou
   double* ws = scratch;
   if (!ws) PPW_HIP(hipMalloc(&ws, sizeof(double) * 2 * (size_t)n * n));
   if (n <= 64)
-    syev_kernel<64><<<1, 64, 0, s>>>(n, A, w, Z, ws, ws + (size_t)n * n);
+    syev_kernel<64, true><<<1, 64, 0, s>>>(n, A, w, Z, ws, ws + (size_t)n * n);
   else
-    syev_kernel<kT><<<1, kT, 0, s>>>(n, A, w, Z, ws, ws + (size_t)n * n);
+    syev_kernel<kT, false><<<1, kT, 0, s>>>(n, A, w, Z, ws, ws + (size_t)n * n);
   hipError_t e = hipGetLastError();
   if (!scratch) {
     (void)hipStreamSynchronize(s);
