@@ -20,6 +20,7 @@
 #include "common.h"
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 namespace ppw {
@@ -72,6 +73,202 @@ __device__ __forceinline__ void tile_coords(int id, int tiles_m, int tiles_n, in
   tn = r / gsize;
 }
 
+// ---------------------------------------------------------------------------
+// FP64 tiles with both operands contiguous along k (the amplitude contraction and its
+// grouped launches): operand tiles go from global memory straight into LDS
+// (global_load_lds_dwordx4: lane l of a wave writes 16 B at the wave's LDS base + 16 l),
+// so no registers hold the next tile and no LDS stores are issued.  A tile row of BK = 16
+// doubles is 8 slots of 16 B; (row r, pair kp) lives in slot r * 8 + (kp ^ ((r >> 1) & 7)),
+// which puts the 16 rows of an MFMA fragment read in 16 different 16-byte bank groups.
+// Lanes choose their source element so that each wave's 64 slots (8 rows) are filled in
+// one instruction.  Ragged tiles (an edge in m, n or k, or rows not 16-byte aligned) are
+// loaded through registers into the same layout.  The two LDS buffers are separate
+// arrays and the loop is unrolled by two, so a buffer being filled and the buffer being
+// read are distinct objects to the compiler.  MFMA operands and their order are those of
+// the register-staged path, so results are bit-identical to it.
+__device__ __forceinline__ int swz16(int r, int kp) { return r * 8 + (kp ^ ((r >> 1) & 7)); }
+
+template <int BM, int BN>
+__device__ __forceinline__ void gemm_tile_dma(const GemmDesc& d, double alpha, const double* __restrict__ A,
+                                              const double* __restrict__ B, double beta, double* __restrict__ C,
+                                              double* __restrict__ W, int splitk, long flat, int split) {
+  constexpr int BK = 16;
+  using acc_t = Mfma<double>::acc_t;
+  constexpr int WTM = BM / 2, WTN = BN / 2;
+  constexpr int TM = WTM / 16, TN = WTN / 16;
+  constexpr int SA = BM * BK, SB = BN * BK;
+  constexpr int CA = BM / 32, CB = BN / 32;  // 1 KB chunks per wave (4 waves, 8 rows a chunk)
+  __shared__ __attribute__((aligned(16))) double As0[SA];
+  __shared__ __attribute__((aligned(16))) double As1[SA];
+  __shared__ __attribute__((aligned(16))) double Bs0[SB];
+  __shared__ __attribute__((aligned(16))) double Bs1[SB];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int tiles_m = (d.M + BM - 1) / BM;
+  const int tiles_n = (d.N + BN - 1) / BN;
+  const long ntiles = (long)tiles_m * tiles_n;
+  const int batch = (int)(flat / ntiles);
+  int tm, tn;
+  tile_coords((int)(flat % ntiles), tiles_m, tiles_n, tm, tn);
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int b1 = batch / d.nb2, b2 = batch % d.nb2;
+  const double* Atile = A + b1 * d.sA1 + b2 * d.sA2 + (long)m0 * d.lda;
+  const double* Btile = B + b1 * d.sB1 + b2 * d.sB2 + (long)n0 * d.ldb;
+  const int nkt = (d.K + BK - 1) / BK;
+  const long total = (long)d.KB * nkt;
+  const long chunk = (total + splitk - 1) / splitk;
+  const long it0 = (long)split * chunk;
+  const long it1 = min(total, it0 + chunk);
+  const int lda32 = (int)d.lda, ldb32 = (int)d.ldb;
+  const int mrem = d.M - m0, nrem = d.N - n0;
+  const bool rows_ok = mrem >= BM && nrem >= BN && (d.lda % 2) == 0 && (d.ldb % 2) == 0 && (d.sAk % 2) == 0 &&
+                       (d.sBk % 2) == 0 && ((uintptr_t)Atile % 16) == 0 && ((uintptr_t)Btile % 16) == 0;
+  // source element (within a tile, k0 = 0) of this lane's slot in each of its chunks
+  int offA[CA], offB[CB];
+#pragma unroll
+  for (int c = 0; c < CA; ++c) {
+    const int sl = (wave + 4 * c) * 64 + lane, r = sl >> 3, kp = (sl & 7) ^ ((r >> 1) & 7);
+    offA[c] = r * lda32 + 2 * kp;
+  }
+#pragma unroll
+  for (int c = 0; c < CB; ++c) {
+    const int sl = (wave + 4 * c) * 64 + lane, r = sl >> 3, kp = (sl & 7) ^ ((r >> 1) & 7);
+    offB[c] = r * ldb32 + 2 * kp;
+  }
+  typedef double pair_t __attribute__((ext_vector_type(2)));
+  // fill buffer (Ab, Bb) with the k tile (kb, kt)
+  auto fill = [&](double* Ab, double* Bb, int kb, int kt) {
+    const int k0 = kt * BK;
+    const double* Ak = Atile + kb * d.sAk + k0;
+    const double* Bk = Btile + kb * d.sBk + k0;
+    const int krem = d.K - k0;
+    if (rows_ok && krem >= BK) {
+#pragma unroll
+      for (int c = 0; c < CA; ++c)
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(Ak + offA[c]),
+                                         (__attribute__((address_space(3))) void*)(Ab + (wave + 4 * c) * 128), 16, 0,
+                                         0);
+#pragma unroll
+      for (int c = 0; c < CB; ++c)
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(Bk + offB[c]),
+                                         (__attribute__((address_space(3))) void*)(Bb + (wave + 4 * c) * 128), 16, 0,
+                                         0);
+    } else {
+      // element-wise guarded loads, zero outside the operand
+#pragma unroll
+      for (int i = 0; i < SA / 2 / kThreads; ++i) {
+        const int pr = i * kThreads + tid, m = pr >> 3, kp = pr & 7;
+        pair_t v;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int kk = 2 * kp + h;
+          v[h] = (m < mrem && kk < krem) ? Ak[m * lda32 + kk] : 0.0;
+        }
+        *reinterpret_cast<pair_t*>(Ab + 2 * swz16(m, kp)) = v;
+      }
+#pragma unroll
+      for (int i = 0; i < SB / 2 / kThreads; ++i) {
+        const int pr = i * kThreads + tid, nn = pr >> 3, kp = pr & 7;
+        pair_t v;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int kk = 2 * kp + h;
+          v[h] = (nn < nrem && kk < krem) ? Bk[nn * ldb32 + kk] : 0.0;
+        }
+        *reinterpret_cast<pair_t*>(Bb + 2 * swz16(nn, kp)) = v;
+      }
+    }
+  };
+
+  acc_t acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+  auto frag = [&](const double* Ab, const double* Bb, int kk, double (&a)[TM], double (&b)[TN]) {
+    const int kr = kk + (lane >> 4);
+#pragma unroll
+    for (int i = 0; i < TM; ++i) a[i] = Ab[2 * swz16(wm * WTM + i * 16 + (lane & 15), kr >> 1) + (kr & 1)];
+#pragma unroll
+    for (int j = 0; j < TN; ++j) b[j] = Bb[2 * swz16(wn * WTN + j * 16 + (lane & 15), kr >> 1) + (kr & 1)];
+  };
+  auto mma = [&](const double (&a)[TM], const double (&b)[TN]) {
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) acc[i][j] = Mfma<double>::mma(a[i], b[j], acc[i][j]);
+  };
+
+  if (it0 < it1) {
+    int kb = (int)(it0 / nkt), kt = (int)(it0 % nkt);
+    fill(As0, Bs0, kb, kt);
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's loads into LDS have landed
+    __syncthreads();
+    // one k tile: prefetch the next into (An, Bn) while the MFMAs read (Ac, Bc)
+    auto step = [&](const double* Ac, const double* Bc, double* An, double* Bn, long it) {
+      const bool more = it + 1 < it1;
+      int nkb = kb, nkt2 = kt + 1;
+      if (nkt2 == nkt) {
+        nkt2 = 0;
+        ++nkb;
+      }
+      if (more) fill(An, Bn, nkb, nkt2);
+      double a0[TM], b0[TN], a1[TM], b1v[TN];
+      frag(Ac, Bc, 0, a0, b0);
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 8) {
+        frag(Ac, Bc, kk + 4, a1, b1v);
+        mma(a0, b0);
+        if (kk + 8 < BK) frag(Ac, Bc, kk + 8, a0, b0);
+        mma(a1, b1v);
+      }
+#pragma unroll
+      for (int g = 0; g + 1 < BK / 4; ++g) {
+#pragma unroll
+        for (int r = 0; r < TM + TN; ++r) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        }
+        if constexpr (TM * TN > TM + TN) __builtin_amdgcn_sched_group_barrier(0x008, TM * TN - (TM + TN), 0);
+      }
+      __builtin_amdgcn_sched_group_barrier(0x008, TM * TN, 0);
+      if (more) __builtin_amdgcn_s_waitcnt(0x0F70);
+      __syncthreads();
+      kb = nkb;
+      kt = nkt2;
+    };
+    for (long it = it0; it < it1; it += 2) {
+      step(As0, Bs0, As1, Bs1, it);
+      if (it + 1 < it1) step(As1, Bs1, As0, Bs0, it + 1);
+    }
+  }
+
+  const long nbatch = (long)d.nb1 * d.nb2;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * WTM + i * 16 + Mfma<double>::row(lane, r);
+        const int col = n0 + wn * WTN + j * 16 + (lane & 15);
+        if (row < d.M && col < d.N) {
+          const double v = acc[i][j][r];
+          if (W) {
+            W[((long)split * nbatch + batch) * ((long)d.M * d.N) + (long)row * d.N + col] = v;
+          } else {
+            double* cp = C + b1 * d.sC1 + b2 * d.sC2 + (long)row * d.ldc + col;
+            double out = alpha * v;
+            if (beta != 0.0) out += beta * (*cp);
+            *cp = out;
+          }
+        }
+      }
+}
+
 // LDS layouts (chosen per operand at compile time, FP64 64 banks x 4 B):
 //  * operand contiguous along k in global memory (A: transA = 0, B: transB = 1):
 //    tile stored [m][BK + 2]; a 16-lane group reads 16 rows at one k: bank offsets
@@ -87,6 +284,10 @@ template <typename T, int BM, int BN, int BK, bool AK, bool BKC>
 __device__ __forceinline__ void gemm_tile(const GemmDesc& d, T alpha, const T* __restrict__ A,
                                           const T* __restrict__ B, T beta, T* __restrict__ C, T* __restrict__ W,
                                           int splitk, long flat, int split) {
+  if constexpr (std::is_same<T, double>::value && AK && BKC && BK == 16) {
+    gemm_tile_dma<BM, BN>(d, alpha, A, B, beta, C, W, splitk, flat, split);
+    return;
+  }
   using acc_t = typename Mfma<T>::acc_t;
   constexpr int PK = 2;   // pad of k-contiguous tiles
   constexpr int PM = 16;  // pad of m/n-contiguous tiles
