@@ -575,12 +575,35 @@ long checked_workgroups(const GemmDesc& d) {
   return wgs;
 }
 
+constexpr long kResident = 512;  // workgroups resident at once: 256 CUs x 2
+
 template <typename T, int BM, int BN, int BK, bool AK, bool BKC, int TAG>
 void launch(const GemmDesc& d, T alpha, const T* A, const T* B, T beta, T* C, hipStream_t s, Workspace ws) {
   const int tiles_m = (d.M + BM - 1) / BM, tiles_n = (d.N + BN - 1) / BN;
   const long nbatch = (long)d.nb1 * d.nb2;
   checked_workgroups<BM, BN, BK>(d);
   const long ntiles = (long)tiles_m * tiles_n;
+  // Wave quantisation: when the last of several waves of tiles would run at most half
+  // full, the trailing tile columns that make up that wave are peeled off into a second
+  // GEMM, which then has too few tiles to fill the chip and is split along k (an ordered,
+  // deterministic reduction); the main GEMM ends on a full wave.  The peeled part keeps
+  // its own kernel symbol (TAG + 2) so that traces tell the two apart.
+  if constexpr (TAG < 2) {
+   if (nbatch == 1 && ws.ptr && ntiles >= 2 * kResident) {
+    const long rem = ntiles % kResident;
+    const int cols = (int)((rem + tiles_m - 1) / tiles_m);
+    if (rem > 0 && rem <= kResident / 2 && cols < tiles_n) {
+      const int nmain = (tiles_n - cols) * BN;
+      GemmDesc dm = d, dr = d;
+      dm.N = nmain;
+      dr.N = d.N - nmain;
+      launch<T, BM, BN, BK, AK, BKC, TAG>(dm, alpha, A, B, beta, C, s, Workspace{});
+      const T* Br = B + (BKC ? (long)nmain * d.ldb : (long)nmain);
+      launch<T, BM, BN, BK, AK, BKC, TAG + 2>(dr, alpha, A, Br, beta, C + nmain, s, ws);
+      return;
+    }
+   }
+  }
   const int nkt = (d.K + BK - 1) / BK;
   const long total = (long)d.KB * nkt;
   // split the reduction when the grid is too small to fill 256 CUs

@@ -83,6 +83,28 @@ def test_gemm_layouts(B, fp32, pads, M, N, K, KB, nb, tA, tB):
         np.testing.assert_allclose(got, exp, rtol=(2e-5 if fp32 else 0), atol=tol)
 
 
+@pytest.mark.parametrize("fp32", [False, True])
+def test_gemm_peeled_tail(B, fp32):
+    """A GEMM of 32 x 34 tiles (1088 workgroups: two full waves of 512 and 64 left over):
+    the two trailing tile columns are peeled into a split-k launch; the result must equal
+    the plain product (k-contiguous operands, the amplitude-contraction layout)."""
+    rng = np.random.default_rng(8)
+    M, N, K = 4096, 128 * 33 + 40, 40
+    A = rng.standard_normal((M, K))
+    Bt = rng.standard_normal((N, K))
+    C0 = rng.standard_normal((M, N))
+    ref = 1.25 * (A @ Bt.T) + 0.5 * C0
+    dt = torch.float32 if fp32 else torch.float64
+    dA = torch.tensor(A, dtype=dt, device="cuda")
+    dB = torch.tensor(Bt, dtype=dt, device="cuda")
+    dC = torch.tensor(C0, dtype=dt, device="cuda")
+    B.gemm(dA, dB, dC, M=M, N=N, K=K, KB=1, nbatch=1, transA=0, lda=K, sA=0, sAk=0, transB=1, ldb=K, sB=0, sBk=0,
+           ldc=N, sC=0, alpha=1.25, beta=0.5, ws_bytes=64 << 20, fp32=fp32)
+    got = dC.double().cpu().numpy()
+    tol = (2e-5 if fp32 else 1e-13) * np.sqrt(K) * 3
+    np.testing.assert_allclose(got, ref, rtol=(2e-5 if fp32 else 0), atol=tol)
+
+
 @pytest.mark.parametrize("n", [1, 2, 3, 5, 24, 34, 37, 64, 65, 130, 400])
 def test_small_syev(B, n):
     rng = np.random.default_rng(n)
