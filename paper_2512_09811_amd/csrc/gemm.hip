@@ -583,13 +583,15 @@ void launch(const GemmDesc& d, T alpha, const T* A, const T* B, T beta, T* C, hi
   const long nbatch = (long)d.nb1 * d.nb2;
   checked_workgroups<BM, BN, BK>(d);
   const long ntiles = (long)tiles_m * tiles_n;
-  // Wave quantisation: when the last of several waves of tiles would run at most half
-  // full, the trailing tile columns that make up that wave are peeled off into a second
-  // GEMM, which then has too few tiles to fill the chip and is split along k (an ordered,
-  // deterministic reduction); the main GEMM ends on a full wave.  The peeled part keeps
-  // its own kernel symbol (TAG + 2) so that traces tell the two apart.
-  if constexpr (TAG < 2) {
-   if (nbatch == 1 && ws.ptr && ntiles >= 2 * kResident) {
+  // Wave quantisation: when the last of several waves of 128 x 128 tiles would run at
+  // most half full, the trailing tile columns that make up that wave are peeled off and
+  // computed with 64 x 64 tiles (four times the workgroups, a quarter of the work each),
+  // so the tail takes about a quarter of a tile's time.  Every output element is
+  // accumulated over the same sequence of MFMA k steps in both tile shapes, so the result
+  // is bit-identical to the unpeeled GEMM.  The peeled part has its own kernel symbol
+  // (TAG + 2) so that traces tell the two apart.
+  if constexpr (TAG < 2 && BM == 128 && BN == 128) {
+   if (nbatch == 1 && ntiles >= 2 * kResident) {
     const long rem = ntiles % kResident;
     const int cols = (int)((rem + tiles_m - 1) / tiles_m);
     if (rem > 0 && rem <= kResident / 2 && cols < tiles_n) {
@@ -599,7 +601,7 @@ void launch(const GemmDesc& d, T alpha, const T* A, const T* B, T beta, T* C, hi
       dr.N = d.N - nmain;
       launch<T, BM, BN, BK, AK, BKC, TAG>(dm, alpha, A, B, beta, C, s, Workspace{});
       const T* Br = B + (BKC ? (long)nmain * d.ldb : (long)nmain);
-      launch<T, BM, BN, BK, AK, BKC, TAG + 2>(dr, alpha, A, Br, beta, C + nmain, s, ws);
+      launch<T, BM / 2, BN / 2, BK, AK, BKC, TAG + 2>(dr, alpha, A, Br, beta, C + nmain, s, Workspace{});
       return;
     }
    }

@@ -86,8 +86,9 @@ def test_gemm_layouts(B, fp32, pads, M, N, K, KB, nb, tA, tB):
 @pytest.mark.parametrize("fp32", [False, True])
 def test_gemm_peeled_tail(B, fp32):
     """A GEMM of 32 x 34 tiles (1088 workgroups: two full waves of 512 and 64 left over):
-    the two trailing tile columns are peeled into a split-k launch; the result must equal
-    the plain product (k-contiguous operands, the amplitude-contraction layout)."""
+    the two trailing tile columns are peeled into a launch of 64 x 64 tiles; the result
+    must equal the plain product (k-contiguous operands, the amplitude-contraction layout)
+    and, with or without a workspace, be bit-identical to the unpeeled GEMM."""
     rng = np.random.default_rng(8)
     M, N, K = 4096, 128 * 33 + 40, 40
     A = rng.standard_normal((M, K))
@@ -103,6 +104,13 @@ def test_gemm_peeled_tail(B, fp32):
     got = dC.double().cpu().numpy()
     tol = (2e-5 if fp32 else 1e-13) * np.sqrt(K) * 3
     np.testing.assert_allclose(got, ref, rtol=(2e-5 if fp32 else 0), atol=tol)
+    # bit-identical to the same product with no peeling (a batch of one GEMM per launch
+    # is never peeled: the same operands as two stacked copies, batch stride 0 on A)
+    dC2 = torch.tensor(np.stack([C0, C0]), dtype=dt, device="cuda")
+    dB2 = torch.stack([dB, dB]).contiguous()
+    B.gemm(dA, dB2, dC2, M=M, N=N, K=K, KB=1, nbatch=2, transA=0, lda=K, sA=0, sAk=0, transB=1, ldb=K,
+           sB=N * K, sBk=0, ldc=N, sC=M * N, alpha=1.25, beta=0.5, ws_bytes=64 << 20, fp32=fp32)
+    assert torch.equal(dC2[0], dC) and torch.equal(dC2[1], dC)
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 5, 24, 34, 37, 64, 65, 130, 400])
