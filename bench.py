@@ -383,7 +383,12 @@ def main():
         "latency_p50_s": float(np.percentile(lat, 50)),
         "latency_p99_s": float(np.percentile(lat, 99)),
         "products_per_window": float(np.mean([r[3]["products"] for res, _ in recs for r in res])),
-        "roofline": {"bound": "mfma", "kernel": "gemm_kernel<double,128,128,16,1> (H = tau G)",
+        "roofline": {"bound": "mfma",
+                     "kernel": ("gemm_kernel<double,128,128,16,1> (H = tau G; a call is the main launch plus a "
+                                "peeled 64x64 tail when its last wave would run at most half full)"
+                                if args.precision == "fp64" else
+                                "gemm_kernel<float,128,128,16,1> and its FP64 refinement passes (H = tau G), "
+                                "priced against the FP32 peak"),
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                      "launches": h_n, "avg_launch_ms": 1e3 * h_sec / max(h_n, 1),
                      "flops_per_launch": h_flops / max(h_n, 1),
