@@ -1139,6 +1139,48 @@ void Solver::run(double* energies, double* vectors, double* osc, pp_solve_info* 
     // Ritz pair (large residual, large folded quotient) next to omega0, and would
     // otherwise be dropped at a restart while farther roots converge.  The inner pairs
     // lead the block, so they get corrections and survive restarts.
+    bool all = false;
+    double worst = 0.0;
+    if (cf_) {
+      // Riesz mode: the subspace is the filtered block's X and Y halves, and its paired
+      // closure holds directions the filter never touched; they give Ritz pairs that do
+      // not converge (residual of order one) and can sit nearer omega0 than true roots.
+      // The window is taken among the pairs whose residual is below 1e-2 (a true
+      // eigenvector inside the contour is in the filtered span, so its Ritz pair
+      // converges): the n_roots nearest of them, all of which must meet the tolerance.
+      std::vector<int> byd(n), rel;
+      std::iota(byd.begin(), byd.end(), 0);
+      std::stable_sort(byd.begin(), byd.end(),
+                       [&](int a, int b) { return std::fabs(R.th[a] - w0_) < std::fabs(R.th[b] - w0_); });
+      for (int j : byd)
+        if (R.rn[j] <= 1e-2) rel.push_back(j);
+      const bool enough = (int)rel.size() >= nr_;
+      const std::vector<int>& src = enough ? rel : byd;
+      out.assign(src.begin(), src.begin() + std::min<int>(nr_, (int)src.size()));
+      tgt = out;
+      inner = out;
+      all = enough && (int)out.size() == nr_;
+      for (int j : out) {
+        all = all && R.rn[j] <= opt_.tol;
+        worst = std::max(worst, R.rn[j]);
+      }
+      // block: the reliable pairs first (nearest first), then the rest by distance
+      blk.clear();
+      for (int j : rel)
+        if ((int)blk.size() < m_) blk.push_back(j);
+      for (int j : byd) {
+        if ((int)blk.size() >= std::min(m_, n)) break;
+        if (std::find(blk.begin(), blk.end(), j) == blk.end()) blk.push_back(j);
+      }
+      // the circle passes halfway between the window's farthest pair and the next one
+      // (reliable pairs when there are enough of them)
+      const std::vector<int>& dref = (int)rel.size() > nr_ ? rel : byd;
+      if ((int)dref.size() > nr_)
+        rad_ = 0.5 * (std::fabs(R.th[dref[nr_ - 1]] - w0_) + std::fabs(R.th[dref[nr_]] - w0_));
+      else if (!dref.empty())
+        rad_ = 1.25 * std::fabs(R.th[dref.back()] - w0_);
+      rad_ = std::max(rad_, 1e-8);
+    } else {
     tgt.assign(order.begin(), order.begin() + std::min(nr_, n));
     double dmax = 0.0;
     for (int j : tgt) dmax = std::max(dmax, std::fabs(R.th[j] - w0_));
@@ -1154,8 +1196,7 @@ void Solver::run(double* energies, double* vectors, double* osc, pp_solve_info* 
       if ((int)blk.size() >= std::min(m_, n)) break;
       if (std::find(blk.begin(), blk.end(), j) == blk.end()) blk.push_back(j);
     }
-    bool all = (int)tgt.size() == nr_;
-    double worst = 0.0;
+    all = (int)tgt.size() == nr_;
     for (int j : tgt) {
       all = all && R.rn[j] <= opt_.tol;
       worst = std::max(worst, R.rn[j]);
@@ -1168,14 +1209,6 @@ void Solver::run(double* energies, double* vectors, double* osc, pp_solve_info* 
     // some inner pair is unresolved)
     if ((int)inner.size() >= nr_) out.assign(inner.begin(), inner.begin() + nr_);
     else out = tgt;
-    if (cf_) {
-      // the circle passes halfway between the window's farthest Ritz value and the next
-      std::vector<double> dist(n);
-      for (int j = 0; j < n; ++j) dist[j] = std::fabs(R.th[j] - w0_);
-      std::sort(dist.begin(), dist.end());
-      if (n > nr_) rad_ = 0.5 * (dist[nr_ - 1] + dist[nr_]);
-      else if (n > 0) rad_ = 1.25 * dist[n - 1];
-      rad_ = std::max(rad_, 1e-8);
     }
     if (worst < 0.5 * best_worst) {
       best_worst = worst;

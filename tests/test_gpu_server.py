@@ -141,3 +141,19 @@ def test_server_stream_shape(P):
     for (s, w, nr), r in zip(reqs, res):
         assert r["n_roots"] == nr and np.all(r["converged"] == 1)
         assert np.all(np.diff(r["energies"]) >= 0)
+
+
+def test_server_riesz_requests(P):
+    """A server whose requests use the Riesz-projector window solve: results match the
+    oracle, and the requests' contour solves share product passes."""
+    systems = _systems()[:3]
+    print(f"[server riesz] {len(systems)} requests", flush=True)
+    with P.Server(max_active=4, method=P.PP_RIESZ) as srv:
+        ids = [srv.submit_system(s, w, nr) for s, w, nr in systems]
+        res = [srv.wait(i) for i in ids]
+        st = srv.stats()
+    assert st["completed"] == len(systems) and st["failed"] == 0
+    for (s, w, nr), r in zip(systems, res):
+        e_ref, f_ref = _oracle(s, w, nr)
+        _check_vs(r["energies"], r["osc"], e_ref, f_ref)
+        assert np.all(r["converged"] == 1) and r["status"] == P.PP_OK
