@@ -107,3 +107,22 @@ def test_window_riesz_batch_and_mixed_precision(P):
             E, V, F, infos = h.window_solve_batch(oms, 6)
         for w, om in enumerate(oms):
             _check(sys, 2, om, 6, E[w], V[w], F[w], infos[w])
+
+
+def test_window_riesz_survey(P):
+    """Seven windows from 0.4 to 1.6 Ha (6 roots each) on three 16/64/192 second-order
+    systems, Riesz mode, batched: every window equals the oracle's."""
+    bad = []
+    for seed in (1, 2, 3):
+        s = gen(seed, 16, 64, 192)
+        A, B, S = dense.assemble(s, 2)
+        om, _, _ = pencil.solve_all(A, B, S)
+        oms = np.linspace(0.4, 1.6, 7)
+        print(f"[riesz survey] seed {seed}", flush=True)
+        with P.Handle.from_system(s, order=2, method=P.PP_RIESZ) as h:
+            E, _, _, infos = h.window_solve_batch(oms, 6, vectors=False, osc=False, allow_unconverged=True)
+        for w, w0 in enumerate(oms):
+            ref = om[pencil.select_window(om, w0, 6)]
+            if not (np.abs(E[w] - ref).max() < 1e-8 and np.all(infos[w]["converged"] == 1)):
+                bad.append((seed, float(w0)))
+    assert not bad, bad
