@@ -569,8 +569,12 @@ long checked_workgroups(const GemmDesc& d) {
   const long nbatch = (long)d.nb1 * d.nb2;
   const long wgs = (long)((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN) * nbatch;
   if (ntiles_total_exceeds(wgs)) throw InvalidArg("gemm: too many workgroups");
-  // per-tile element offsets are 32-bit inside the kernel
-  if ((double)d.lda * std::max(BM, BK) + d.K >= 2147483647.0 || (double)d.ldb * std::max(BN, BK) + d.K >= 2147483647.0)
+  // per-tile element offsets are 32-bit inside the kernel: rows of a tile that lie
+  // outside the operand are never addressed, so a k-contiguous operand needs
+  // min(M, BM) rows of lda, an m-contiguous one BK rows
+  const double ra = d.transA == 0 ? (double)std::min(d.M, BM) * d.lda + BK : (double)BK * d.lda + BM;
+  const double rb = d.transB != 0 ? (double)std::min(d.N, BN) * d.ldb + BK : (double)BK * d.ldb + BN;
+  if (ra >= 2147483647.0 || rb >= 2147483647.0 || d.lda >= 2147483647L || d.ldb >= 2147483647L)
     throw InvalidArg("gemm: leading dimension too large for 32-bit tile offsets");
   return wgs;
 }

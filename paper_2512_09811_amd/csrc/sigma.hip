@@ -511,16 +511,22 @@ void contract(Context& c, const Ops<T>& t, Emit<T>& e, int order, int k, const T
   }
   const long kX = (long)k * X;
   auto outputs = [&](const T* H, int i0, int ib) {
-    // BV[q][i][a] += sum_(c,P) H[(i,c)][(q,P)] Bvv[P][c][a]    rows i0..i0+ib-1
+    // BV[q][i][a] += sum_(c,P) H[(i,c)][(q,P)] Bvv[P][c][a]    rows i0..i0+ib-1; the row
+    // stride of H is v k X, so the rows go in chunks whose in-tile offsets fit 32 bits
     {
-      GemmDesc d = gd(ib, v, X, 0, (long)v * kX, 0, (long)v * v, v);
-      d.KB = v;
-      d.sAk = kX;
-      d.sBk = v;
-      d.nb1 = k;
-      d.sA1 = X;
-      d.sC1 = N;
-      e.gemm(d, one, H, t.Bvv, one, BV + (size_t)i0 * v, c.ws);
+      const long lda = (long)v * kX;
+      const int rchunk = (int)std::max<long>(1, std::min<long>(ib, (2147483647L - 64) / lda - 1));
+      for (int r0 = 0; r0 < ib; r0 += rchunk) {
+        const int rn = std::min(rchunk, ib - r0);
+        GemmDesc d = gd(rn, v, X, 0, lda, 0, (long)v * v, v);
+        d.KB = v;
+        d.sAk = kX;
+        d.sBk = v;
+        d.nb1 = k;
+        d.sA1 = X;
+        d.sC1 = N;
+        e.gemm(d, one, H + (size_t)r0 * lda, t.Bvv, one, BV + (size_t)(i0 + r0) * v, c.ws);
+      }
     }
     // BV[q][i][a] -= sum_(kk,P) Boo[P][i][kk] H[(kk,a)][(q,P)]   kk in i0..i0+ib-1
     {

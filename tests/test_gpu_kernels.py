@@ -113,6 +113,32 @@ def test_gemm_peeled_tail(B, fp32):
     assert torch.equal(dC2[0], dC) and torch.equal(dC2[1], dC)
 
 
+@pytest.mark.parametrize("fp32", [False, True])
+def test_gemm_long_rows(B, fp32):
+    """A k-contiguous left operand with few rows and a row stride of 2^28 + 64 elements
+    (the layout of the amplitude strip against the B^vv factors at large sizes): a 128-row
+    tile would span more than 2^31 elements, but only the 5 existing rows are addressed, so
+    the product runs and matches; 16 such rows exceed 32-bit in-tile offsets and are
+    rejected before any launch."""
+    rng = np.random.default_rng(11)
+    M, N, K, lda = 5, 200, 40, (1 << 28) + 64
+    dt = torch.float32 if fp32 else torch.float64
+    A = rng.standard_normal((M, K))
+    Bt = rng.standard_normal((N, K))
+    dA = torch.zeros((M - 1) * lda + K, dtype=dt, device="cuda")
+    for m in range(M):
+        dA[m * lda:m * lda + K] = torch.tensor(A[m], dtype=dt)
+    dB = torch.tensor(Bt, dtype=dt, device="cuda")
+    dC = torch.zeros((M, N), dtype=dt, device="cuda")
+    B.gemm(dA, dB, dC, M=M, N=N, K=K, transA=0, lda=lda, transB=1, ldb=K, ldc=N, fp32=fp32)
+    tol = (2e-5 if fp32 else 1e-13) * np.sqrt(K) * 3
+    np.testing.assert_allclose(dC.double().cpu().numpy(), A @ Bt.T, rtol=(2e-5 if fp32 else 0), atol=tol)
+    del dA
+    small = torch.zeros(64, dtype=dt, device="cuda")
+    with pytest.raises(B.PPError, match="32-bit tile offsets"):
+        B.gemm(small, dB, dC, M=16, N=N, K=K, transA=0, lda=lda, transB=1, ldb=K, ldc=N, fp32=fp32)
+
+
 @pytest.mark.parametrize("n", [1, 2, 3, 5, 24, 34, 37, 64, 65, 130, 400])
 def test_small_syev(B, n):
     rng = np.random.default_rng(n)
