@@ -304,7 +304,8 @@ pp_status pp_server_destroy(pp_server* srv);
 const char* pp_server_last_error(const pp_server* srv);
 
 const char* pp_status_string(pp_status s);
-/* Last error message of the handle (NULL handle: last error of pp_setup in this thread). */
+/* Last error message of the handle (NULL handle: last error, in this thread, of a call that
+   takes no handle: pp_setup, pp_spectrum and the handle-less test hooks). */
 const char* pp_last_error(const pp_handle* h);
 
 #ifdef __cplusplus

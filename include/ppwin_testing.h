@@ -2,7 +2,8 @@
  * Internal entry points of the ppwin library that the test-suite calls to check
  * single building blocks against plain references.  They are exported with the
  * ppint_ prefix, take device pointers, run synchronously on the default stream
- * and return a pp_status like the public API.  They are not part of the stable
+ * and return a pp_status like the public API; hooks without a handle leave their error
+ * message where pp_last_error(NULL) reads it.  They are not part of the stable
  * interface.
  */
 #ifndef PPWIN_TESTING_H

@@ -240,8 +240,8 @@ pp_status pp_exciton_dos(pp_handle* h, int32_t n_bins, const double* edges, doub
 
 pp_status pp_spectrum(int32_t n, const double* energies, const double* osc, int32_t n_omega, const double* omega,
                       double eta, double* out) {
-  std::string err;
-  return guarded(&err, [&] {
+  g_setup_error.clear();
+  return guarded(&g_setup_error, [&] {
     if (n < 0 || n_omega < 0) throw ppw::InvalidArg("negative size");
     if (!(eta > 0.0) || !std::isfinite(eta)) throw ppw::InvalidArg("eta must be positive");
     if ((n > 0 && (!energies || !osc)) || (n_omega > 0 && (!omega || !out))) throw ppw::InvalidArg("NULL array");
@@ -283,9 +283,9 @@ pp_status ppint_gemm(int32_t fp32, int32_t M, int32_t N, int32_t K, int32_t KB, 
                      int64_t lda, int64_t sA, int64_t sAk, int32_t transB, int64_t ldb, int64_t sB, int64_t sBk,
                      int64_t ldc, int64_t sC, double alpha, const void* A, const void* B, double beta, void* C,
                      uint64_t ws_bytes) {
-  std::string err;
+  g_setup_error.clear();
   void* ws = nullptr;
-  pp_status st = guarded(&err, [&] {
+  pp_status st = guarded(&g_setup_error, [&] {
     ppw::GemmDesc d;
     d.M = M;
     d.N = N;
@@ -319,8 +319,8 @@ pp_status ppint_gemm(int32_t fp32, int32_t M, int32_t N, int32_t K, int32_t KB, 
 }
 
 pp_status ppint_gemm_group(int32_t fp32, int32_t n, const ppint_gemm_member* m, int32_t* grouped_launches) {
-  std::string err;
-  return guarded(&err, [&] {
+  g_setup_error.clear();
+  return guarded(&g_setup_error, [&] {
     if (n < 1 || !m) throw ppw::InvalidArg("ppint_gemm_group: no members");
     auto desc = [](const ppint_gemm_member& x) {
       ppw::GemmDesc d;
@@ -365,9 +365,9 @@ pp_status ppint_gemm_group(int32_t fp32, int32_t n, const ppint_gemm_member* m, 
 
 pp_status ppint_partial_syev(int32_t n, const double* A, double target, int32_t p, double* lam, double* Z,
                              int32_t* q) {
-  std::string err;
+  g_setup_error.clear();
   double* scr = nullptr;
-  pp_status st = guarded(&err, [&] {
+  pp_status st = guarded(&g_setup_error, [&] {
     PPW_HIP(hipMalloc(&scr, sizeof(double) * ppw::partial_syev_scratch(n, p)));
     const int got = ppw::partial_syev(n, A, target, p, lam, Z, scr, nullptr);
     PPW_HIP(hipDeviceSynchronize());
@@ -378,16 +378,16 @@ pp_status ppint_partial_syev(int32_t n, const double* A, double target, int32_t 
 }
 
 pp_status ppint_syev(int32_t n, const double* A, double* w, double* Z) {
-  std::string err;
-  return guarded(&err, [&] {
+  g_setup_error.clear();
+  return guarded(&g_setup_error, [&] {
     ppw::small_syev(n, A, w, Z, nullptr);
     PPW_HIP(hipDeviceSynchronize());
   });
 }
 
 pp_status ppint_cholesky(int32_t n, const double* A, double* L) {
-  std::string err;
-  return guarded(&err, [&] {
+  g_setup_error.clear();
+  return guarded(&g_setup_error, [&] {
     ppw::small_cholesky(n, A, L, nullptr, nullptr);
     PPW_HIP(hipDeviceSynchronize());
   });

@@ -68,5 +68,5 @@ def test_spectrum_host_entry():
     assert abs(integral - f.sum()) < tails
     peak = P.spectrum(e, f, np.array([2.0]), eta)[0]
     assert abs(peak - f[3] / (np.pi * eta)) < 1e-3 * peak
-    with pytest.raises(P.PPError):
+    with pytest.raises(P.PPError, match="eta must be positive"):
         P.spectrum(e, f, w[:10], 0.0)
