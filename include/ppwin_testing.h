@@ -27,6 +27,14 @@ pp_status ppint_gemm(int32_t fp32, int32_t M, int32_t N, int32_t K, int32_t KB, 
                      int64_t ldc, int64_t sC, double alpha, const void* A, const void* B, double beta, void* C,
                      uint64_t ws_bytes);
 
+/* ppint_gemm without batches or outer reduction, with C rows and columns split into
+ * index pairs: C(m,n) = C[(m / cRm) * cSm + (m % cRm) * ldc + (n / cRn) * cSn + n % cRn]
+ * (cRm = 0: m * ldc; cRn = 0: n).  Errors: PP_EINVAL for a negative split or a
+ * shape the kernel cannot address. */
+pp_status ppint_gemm_cmap(int32_t fp32, int32_t M, int32_t N, int32_t K, int32_t transA, int64_t lda, int32_t transB,
+                          int64_t ldb, int64_t ldc, int32_t cRm, int64_t cSm, int32_t cRn, int64_t cSn, double alpha,
+                          const void* A, const void* B, double beta, void* C, uint64_t ws_bytes);
+
 /* One member of ppint_gemm_group (layouts as in ppint_gemm, no batch). */
 typedef struct {
   int32_t M, N, K, transA, transB;

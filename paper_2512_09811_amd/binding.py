@@ -125,6 +125,9 @@ def lib() -> C.CDLL:
         L.ppint_gemm.argtypes = [i32, i32, i32, i32, i32, i32, i32, i64, i64, i64, i32, i64, i64, i64, i64, i64,
                                  dbl, vp, vp, dbl, vp, u64]
         L.ppint_gemm.restype = C.c_int
+        L.ppint_gemm_cmap.argtypes = [i32, i32, i32, i32, i32, i64, i32, i64, i64, i32, i64, i32, i64, dbl, vp, vp,
+                                      dbl, vp, C.c_uint64]
+        L.ppint_gemm_cmap.restype = C.c_int
         L.ppint_gemm_group.argtypes = [i32, i32, C.POINTER(ppint_gemm_member), C.POINTER(i32)]
         L.ppint_gemm_group.restype = C.c_int
         L.ppint_partial_syev.argtypes = [i32, vp, dbl, i32, vp, vp, C.POINTER(i32)]
@@ -342,6 +345,14 @@ def gemm(A, B, C_, *, M, N, K, KB=1, nbatch=1, transA=0, lda, sA=0, sAk=0, trans
     """Library GEMM on torch device tensors (internal test hook)."""
     st = lib().ppint_gemm(1 if fp32 else 0, M, N, K, KB, nbatch, transA, lda, sA, sAk, transB, ldb, sB, sBk, ldc, sC,
                           alpha, A.data_ptr(), B.data_ptr(), beta, C_.data_ptr(), ws_bytes)
+    _check(st)
+
+
+def gemm_cmap(A, B, C_, *, M, N, K, transA=0, lda, transB=0, ldb, ldc, cRm=0, cSm=0, cRn=0, cSn=0, alpha=1.0,
+              beta=0.0, ws_bytes=0, fp32=False):
+    """Library GEMM with C rows/columns split into index pairs (internal test hook)."""
+    st = lib().ppint_gemm_cmap(1 if fp32 else 0, M, N, K, transA, lda, transB, ldb, ldc, cRm, cSm, cRn, cSn, alpha,
+                               A.data_ptr(), B.data_ptr(), beta, C_.data_ptr(), ws_bytes)
     _check(st)
 
 

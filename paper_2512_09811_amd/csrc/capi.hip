@@ -318,6 +318,41 @@ pp_status ppint_gemm(int32_t fp32, int32_t M, int32_t N, int32_t K, int32_t KB, 
   return st;
 }
 
+pp_status ppint_gemm_cmap(int32_t fp32, int32_t M, int32_t N, int32_t K, int32_t transA, int64_t lda, int32_t transB,
+                          int64_t ldb, int64_t ldc, int32_t cRm, int64_t cSm, int32_t cRn, int64_t cSn, double alpha,
+                          const void* A, const void* B, double beta, void* C, uint64_t ws_bytes) {
+  g_setup_error.clear();
+  void* ws = nullptr;
+  pp_status st = guarded(&g_setup_error, [&] {
+    ppw::GemmDesc d;
+    d.M = M;
+    d.N = N;
+    d.K = K;
+    d.transA = transA;
+    d.lda = lda;
+    d.transB = transB;
+    d.ldb = ldb;
+    d.ldc = ldc;
+    d.cRm = cRm;
+    d.cSm = cSm;
+    d.cRn = cRn;
+    d.cSn = cSn;
+    ppw::Workspace w;
+    if (ws_bytes) {
+      PPW_HIP(hipMalloc(&ws, ws_bytes));
+      w.ptr = ws;
+      w.bytes = ws_bytes;
+    }
+    if (fp32)
+      ppw::gemm_f32(d, (float)alpha, (const float*)A, (const float*)B, (float)beta, (float*)C, nullptr, w);
+    else
+      ppw::gemm_f64(d, alpha, (const double*)A, (const double*)B, beta, (double*)C, nullptr, w);
+    PPW_HIP(hipDeviceSynchronize());
+  });
+  if (ws) (void)hipFree(ws);
+  return st;
+}
+
 pp_status ppint_gemm_group(int32_t fp32, int32_t n, const ppint_gemm_member* m, int32_t* grouped_launches) {
   g_setup_error.clear();
   return guarded(&g_setup_error, [&] {

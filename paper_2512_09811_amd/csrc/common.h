@@ -53,6 +53,11 @@ struct NotSupported : std::runtime_error {
 // beta == 0 never reads C.  The outer loop lets a contraction index that is
 // split across two strides (e.g. (j, P) with P between j and the inner index)
 // be reduced without a transpose.
+//
+// Rows and columns of C may each be pairs of indices with their own strides:
+// with cRm > 0 row m is placed at (m / cRm) * cSm + (m % cRm) * ldc, with cRn > 0
+// column n at (n / cRn) * cSn + n % cRn (0 leaves them plain), so a product whose
+// output is a strided block of a larger array is written in place.
 // ---------------------------------------------------------------------------
 struct GemmDesc {
   int M = 0, N = 0, K = 0, KB = 1;
@@ -62,6 +67,8 @@ struct GemmDesc {
   long sA1 = 0, sA2 = 0, sAk = 0;
   long sB1 = 0, sB2 = 0, sBk = 0;
   long sC1 = 0, sC2 = 0;
+  int cRm = 0, cRn = 0;
+  long cSm = 0, cSn = 0;
 };
 
 // Workspace used by split-K launches (owned by the caller, bytes).

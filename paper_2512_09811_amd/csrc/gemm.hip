@@ -88,6 +88,52 @@ __device__ __forceinline__ void tile_coords(int id, int tiles_m, int tiles_n, in
 // the register-staged path, so results are bit-identical to it.
 __device__ __forceinline__ int swz16(int r, int kp) { return r * 8 + (kp ^ ((r >> 1) & 7)); }
 
+// Offset of index x along a C dimension that may be a pair (x / R, x % R) with strides
+// (S, unit); R = 0 gives x * unit.  The quotient comes from a double product and one
+// correction, exact for every int x.
+__device__ __forceinline__ long c_index(int x, int R, long S, long unit) {
+  if (R == 0) return (long)x * unit;
+  int q = (int)((double)x * (1.0 / (double)R));
+  int r = x - q * R;
+  if (r < 0) {
+    --q;
+    r += R;
+  } else if (r >= R) {
+    ++q;
+    r -= R;
+  }
+  return (long)q * S + (long)r * unit;
+}
+
+// Epilogue of a tile whose C rows or columns are mapped (no split-K workspace): column
+// offsets once per thread, row offsets once per accumulator row.
+template <typename T, typename Acc, int TM, int TN, int WTM, int WTN>
+__device__ __forceinline__ void store_mapped(const GemmDesc& d, T alpha, T beta, T* __restrict__ Cb, int m0, int n0,
+                                             int wm, int wn, int lane, const Acc (&acc)[TM][TN]) {
+  long coff[TN];
+#pragma unroll
+  for (int j = 0; j < TN; ++j) {
+    const int col = n0 + wn * WTN + j * 16 + (lane & 15);
+    coff[j] = col < d.N ? c_index(col, d.cRn, d.cSn, 1) : -1;
+  }
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = m0 + wm * WTM + i * 16 + Mfma<T>::row(lane, r);
+      if (row >= d.M) continue;
+      const long ro = c_index(row, d.cRm, d.cSm, d.ldc);
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        if (coff[j] < 0) continue;
+        T* cp = Cb + ro + coff[j];
+        T out = alpha * acc[i][j][r];
+        if (beta != T(0)) out += beta * (*cp);
+        *cp = out;
+      }
+    }
+}
+
 template <int BM, int BN>
 __device__ __forceinline__ void gemm_tile_dma(const GemmDesc& d, double alpha, const double* __restrict__ A,
                                               const double* __restrict__ B, double beta, double* __restrict__ C,
@@ -247,6 +293,11 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmDesc& d, double alpha, c
   }
 
   const long nbatch = (long)d.nb1 * d.nb2;
+  if (!W && (d.cRm | d.cRn)) {
+    store_mapped<double, acc_t, TM, TN, WTM, WTN>(d, alpha, beta, C + b1 * d.sC1 + b2 * d.sC2, m0, n0, wm, wn, lane,
+                                                 acc);
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -480,6 +531,10 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& d, T alpha, const T* _
   }
 
   const long nbatch = (long)d.nb1 * d.nb2;
+  if (!W && (d.cRm | d.cRn)) {
+    store_mapped<T, acc_t, TM, TN, WTM, WTN>(d, alpha, beta, C + b1 * d.sC1 + b2 * d.sC2, m0, n0, wm, wn, lane, acc);
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -553,7 +608,7 @@ __global__ void splitk_reduce_kernel(GemmDesc d, T alpha, T beta, const T* __res
     T s = T(0);
     for (int k = 0; k < splitk; ++k) s += W[((long)k * nbatch + batch) * per + rc];
     const int b1 = (int)(batch / d.nb2), b2 = (int)(batch % d.nb2);
-    T* cp = C + b1 * d.sC1 + b2 * d.sC2 + (long)row * d.ldc + col;
+    T* cp = C + b1 * d.sC1 + b2 * d.sC2 + c_index(row, d.cRm, d.cSm, d.ldc) + c_index(col, d.cRn, d.cSn, 1);
     T out = alpha * s;
     if (beta != T(0)) out += beta * (*cp);
     *cp = out;
@@ -576,6 +631,7 @@ long checked_workgroups(const GemmDesc& d) {
   const double rb = d.transB != 0 ? (double)std::min(d.N, BN) * d.ldb + BK : (double)BK * d.ldb + BN;
   if (ra >= 2147483647.0 || rb >= 2147483647.0 || d.lda >= 2147483647L || d.ldb >= 2147483647L)
     throw InvalidArg("gemm: leading dimension too large for 32-bit tile offsets");
+  if (d.cRm < 0 || d.cRn < 0) throw InvalidArg("gemm: negative C index split");
   return wgs;
 }
 
@@ -595,7 +651,7 @@ void launch(const GemmDesc& d, T alpha, const T* A, const T* B, T beta, T* C, hi
   // is bit-identical to the unpeeled GEMM.  The peeled part has its own kernel symbol
   // (TAG + 2) so that traces tell the two apart.
   if constexpr (TAG < 2 && BM == 128 && BN == 128) {
-   if (nbatch == 1 && ntiles >= 2 * kResident) {
+   if (nbatch == 1 && ntiles >= 2 * kResident && d.cRn == 0) {
     const long rem = ntiles % kResident;
     const int cols = (int)((rem + tiles_m - 1) / tiles_m);
     if (rem > 0 && rem <= kResident / 2 && cols < tiles_n) {

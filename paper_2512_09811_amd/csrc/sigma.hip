@@ -451,15 +451,16 @@ void contract(Context& c, const Ops<T>& t, Emit<T>& e, int order, int k, const T
   // J: c[P][q] = sum_ia Bov[P][ia] V[q][ia];  J[q][ia] = sum_P c[P][q] Bov[P][ia]
   e.gemm(gd(X, k, (int)N, 0, N, 1, N, k), one, t.Bov, V, zero, t.c, c.ws);
   e.gemm(gd(k, (int)N, X, 1, k, 0, N, N), one, t.c, t.Bov, zero, J, c.ws);
-  // G1[q][P][j][d] = sum_b V[q][j][b] Bvv[P][b][d]
+  // G1[q][P][j][d] = sum_b V[q][j][b] Bvv[P][b][d].  B^vv_P is symmetric, so Bvv read as
+  // [(P,d)][b] is the k-contiguous right operand of one GEMM with rows (q,j) = k o and
+  // columns (P,d) = X v; the C index split writes row (q,j) at q X N + j v and column
+  // (P,d) at P N + d, i.e. into the [q][P][j][d] layout.
   {
-    GemmDesc d = gd(o, v, v, 0, v, 0, v, v);
-    d.nb1 = k;
-    d.nb2 = X;
-    d.sA1 = N;
-    d.sB2 = (long)v * v;
-    d.sC1 = (long)X * N;
-    d.sC2 = N;
+    GemmDesc d = gd(k * o, X * v, v, 0, v, 1, v, v);
+    d.cRm = o;
+    d.cSm = (long)X * N;
+    d.cRn = v;
+    d.cSn = N;
     e.gemm(d, one, V, t.Bvv, zero, t.G, c.ws);
   }
   // AV = -K_A(V) = -sum_P Boo_P G1_P

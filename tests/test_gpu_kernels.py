@@ -113,6 +113,62 @@ def test_gemm_peeled_tail(B, fp32):
     assert torch.equal(dC2[0], dC) and torch.equal(dC2[1], dC)
 
 
+def _cmap_offsets(M, N, ldc, cRm, cSm, cRn, cSn):
+    m, n = np.arange(M)[:, None], np.arange(N)[None, :]
+    ro = (m // cRm) * cSm + (m % cRm) * ldc if cRm else m * ldc
+    co = (n // cRn) * cSn + n % cRn if cRn else n
+    return ro + co
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+@pytest.mark.parametrize("case", ["g1_small", "g1_tiles", "rows_only", "cols_only", "splitk"])
+def test_gemm_cmap(B, fp32, case):
+    """C rows and columns split into index pairs: every mapped element equals the plain
+    product (alpha, beta applied), every other element of the output array is left as it
+    was.  g1_* write rows (q, j) and columns (P, d) of V B^vv into a [q][P][j][d] array,
+    across several 128 x 128 tiles with the direct-to-LDS loads (g1_tiles) and in one
+    ragged 64 x 64 tile (g1_small); splitk maps through the split-K reduction."""
+    rng = np.random.default_rng({"g1_small": 1, "g1_tiles": 2, "rows_only": 3, "cols_only": 4, "splitk": 5}[case])
+    beta = 0.0
+    if case in ("g1_small", "g1_tiles"):
+        o, v, X, k = (6, 10, 5, 3) if case == "g1_small" else (40, 160, 20, 4)
+        M, N, K = k * o, X * v, v
+        ldc, cRm, cSm, cRn, cSn = v, o, X * o * v, v, o * v
+        size = k * X * o * v
+    elif case == "rows_only":
+        M, N, K = 200, 96, 48
+        ldc, cRm, cSm, cRn, cSn = 100, 50, 50 * 100 + 7, 0, 0
+        size = 4 * (50 * 100 + 7)
+        beta = 0.5
+    elif case == "cols_only":
+        M, N, K = 130, 300, 36
+        ldc, cRm, cSm, cRn, cSn = 4 * 80, 0, 0, 75, 80
+        size = M * ldc
+        beta = -1.0
+    else:
+        M, N, K = 40, 96, 6000
+        ldc, cRm, cSm, cRn, cSn = 32, 8, 40 * 32, 32, 8 * 32
+        size = 5 * 40 * 32
+        beta = 0.25
+    A = rng.standard_normal((M, K))
+    Bt = rng.standard_normal((N, K))
+    C0 = rng.standard_normal(size)
+    off = _cmap_offsets(M, N, ldc, cRm, cSm, cRn, cSn)
+    assert off.max() < size and len(np.unique(off)) == M * N
+    exp = C0.copy()
+    exp[off] = 1.5 * (A @ Bt.T) + beta * C0[off]
+    dt = torch.float32 if fp32 else torch.float64
+    dA, dB, dC = (torch.tensor(x, dtype=dt, device="cuda") for x in (A, Bt, C0))
+    B.gemm_cmap(dA, dB, dC, M=M, N=N, K=K, transA=0, lda=K, transB=1, ldb=K, ldc=ldc, cRm=cRm, cSm=cSm, cRn=cRn,
+                cSn=cSn, alpha=1.5, beta=beta, ws_bytes=64 << 20, fp32=fp32)
+    got = dC.double().cpu().numpy()
+    tol = (2e-5 if fp32 else 1e-13) * np.sqrt(K) * 3
+    np.testing.assert_allclose(got, exp if not fp32 else exp, rtol=(2e-5 if fp32 else 0), atol=tol)
+    untouched = np.ones(size, bool)
+    untouched[off] = False
+    assert np.array_equal(got[untouched], C0.astype(np.float32 if fp32 else np.float64)[untouched].astype(np.float64))
+
+
 @pytest.mark.parametrize("fp32", [False, True])
 def test_gemm_long_rows(B, fp32):
     """A k-contiguous left operand with few rows and a row stride of 2^28 + 64 elements
