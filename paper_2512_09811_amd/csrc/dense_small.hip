@@ -474,14 +474,14 @@ __global__ __launch_bounds__(kT) void tridiag_kernel(int n, const double* __rest
         double* Wc = W + (long)(k + 1) * n + (k + 1 + c);  // element (row r, this column) at Wc[r * n]
         double acc = 0.0;
         int r = 1;
-        // eight rows per batch: the loads are issued before any store of the batch, so
+        // twelve rows per batch: the loads are issued before any store of the batch, so
         // they are in flight together (a store to W could otherwise alias a later load)
-        for (; r + 8 <= m; r += 8) {
-          double w[8];
+        for (; r + 12 <= m; r += 12) {
+          double w[12];
 #pragma unroll
-          for (int t = 0; t < 8; ++t) w[t] = Wc[(long)(r + t) * n];
+          for (int t = 0; t < 12; ++t) w[t] = Wc[(long)(r + t) * n];
 #pragma unroll
-          for (int t = 0; t < 8; ++t) {
+          for (int t = 0; t < 12; ++t) {
             w[t] = w[t] - 2.0 * (u[r + t] * qc + q[r + t] * uc);
             Wc[(long)(r + t) * n] = w[t];
             if (nref) acc += w[t] * un[r + t - 1];
