@@ -57,7 +57,12 @@ struct NotSupported : std::runtime_error {
 // Rows and columns of C may each be pairs of indices with their own strides:
 // with cRm > 0 row m is placed at (m / cRm) * cSm + (m % cRm) * ldc, with cRn > 0
 // column n at (n / cRn) * cSn + n % cRn (0 leaves them plain), so a product whose
-// output is a strided block of a larger array is written in place.
+// output is a strided block of a larger array is written in place.  With a column
+// split, column n is mapped as column cBn + n (a launch covering part of the columns).
+//
+// splitk > 0 fixes the number of reduction splits (1: none; the workspace must hold
+// splitk * M * N * batches elements); 0 lets the launch choose.  tile = 64 selects the
+// 64 x 64 tiles whatever the shape; 0 chooses by shape.
 // ---------------------------------------------------------------------------
 struct GemmDesc {
   int M = 0, N = 0, K = 0, KB = 1;
@@ -67,8 +72,9 @@ struct GemmDesc {
   long sA1 = 0, sA2 = 0, sAk = 0;
   long sB1 = 0, sB2 = 0, sBk = 0;
   long sC1 = 0, sC2 = 0;
-  int cRm = 0, cRn = 0;
+  int cRm = 0, cRn = 0, cBn = 0;
   long cSm = 0, cSn = 0;
+  int splitk = 0, tile = 0;
 };
 
 // Workspace used by split-K launches (owned by the caller, bytes).
@@ -87,6 +93,11 @@ void gemm_f64_hhat(const GemmDesc& d, double alpha, const double* A, const doubl
                    hipStream_t s, Workspace ws = {});
 void gemm_f32_hhat(const GemmDesc& d, float alpha, const float* A, const float* B, float beta, float* C,
                    hipStream_t s, Workspace ws = {});
+
+// Number of reduction splits a GEMM launch of d chooses by itself with a workspace of
+// ws_bytes (FP64 or FP32 elements), so that an equivalent product laid out differently
+// can be given the same splits (splitk) and round identically.
+int gemm_auto_splitk(const GemmDesc& d, size_t ws_bytes, bool fp32);
 
 // Algorithmic flop count of a GemmDesc (2 per multiply-add).
 // One GEMM of a set issued together (C = alpha op(A) op(B) + beta C); tag 1 selects the

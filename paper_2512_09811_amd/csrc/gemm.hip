@@ -114,7 +114,7 @@ __device__ __forceinline__ void store_mapped(const GemmDesc& d, T alpha, T beta,
 #pragma unroll
   for (int j = 0; j < TN; ++j) {
     const int col = n0 + wn * WTN + j * 16 + (lane & 15);
-    coff[j] = col < d.N ? c_index(col, d.cRn, d.cSn, 1) : -1;
+    coff[j] = col < d.N ? c_index(col + d.cBn, d.cRn, d.cSn, 1) : -1;
   }
 #pragma unroll
   for (int i = 0; i < TM; ++i)
@@ -608,7 +608,7 @@ __global__ void splitk_reduce_kernel(GemmDesc d, T alpha, T beta, const T* __res
     T s = T(0);
     for (int k = 0; k < splitk; ++k) s += W[((long)k * nbatch + batch) * per + rc];
     const int b1 = (int)(batch / d.nb2), b2 = (int)(batch % d.nb2);
-    T* cp = C + b1 * d.sC1 + b2 * d.sC2 + c_index(row, d.cRm, d.cSm, d.ldc) + c_index(col, d.cRn, d.cSn, 1);
+    T* cp = C + b1 * d.sC1 + b2 * d.sC2 + c_index(row, d.cRm, d.cSm, d.ldc) + c_index(d.cRn ? col + d.cBn : col, d.cRn, d.cSn, 1);
     T out = alpha * s;
     if (beta != T(0)) out += beta * (*cp);
     *cp = out;
@@ -619,6 +619,17 @@ inline bool ntiles_total_exceeds(long n) { return n <= 0 || n > 2147483647L; }
 
 // Workgroups of one GEMM at tile shape BM x BN (before split-K); checks the limits
 // the kernel relies on.
+// Reduction splits when the grid is too small to fill 256 CUs: enough for about 1024
+// workgroups, at least 4 k tiles per split, within the workspace, at most 256.
+int auto_splitk(long wgs, long total, size_t per, size_t ws_bytes) {
+  if (wgs >= 512 || total < 8) return 1;
+  long want = (1024 + wgs - 1) / wgs;
+  want = std::min<long>(want, total / 4);
+  if (per > 0) want = std::min<long>(want, (long)(ws_bytes / per));
+  want = std::min<long>(want, 256);
+  return want >= 2 ? (int)want : 1;
+}
+
 template <int BM, int BN, int BK>
 long checked_workgroups(const GemmDesc& d) {
   const long nbatch = (long)d.nb1 * d.nb2;
@@ -651,7 +662,7 @@ void launch(const GemmDesc& d, T alpha, const T* A, const T* B, T beta, T* C, hi
   // is bit-identical to the unpeeled GEMM.  The peeled part has its own kernel symbol
   // (TAG + 2) so that traces tell the two apart.
   if constexpr (TAG < 2 && BM == 128 && BN == 128) {
-   if (nbatch == 1 && ntiles >= 2 * kResident && d.cRn == 0) {
+   if (nbatch == 1 && ntiles >= 2 * kResident && d.splitk <= 1) {
     const long rem = ntiles % kResident;
     const int cols = (int)((rem + tiles_m - 1) / tiles_m);
     if (rem > 0 && rem <= kResident / 2 && cols < tiles_n) {
@@ -661,23 +672,24 @@ void launch(const GemmDesc& d, T alpha, const T* A, const T* B, T beta, T* C, hi
       dr.N = d.N - nmain;
       launch<T, BM, BN, BK, AK, BKC, TAG>(dm, alpha, A, B, beta, C, s, Workspace{});
       const T* Br = B + (BKC ? (long)nmain * d.ldb : (long)nmain);
-      launch<T, BM / 2, BN / 2, BK, AK, BKC, TAG + 2>(dr, alpha, A, Br, beta, C + nmain, s, Workspace{});
+      T* Cr = C + nmain;
+      if (d.cRn) {  // mapped columns: the tail maps its columns from nmain on
+        dr.cBn = d.cBn + nmain;
+        Cr = C;
+      }
+      launch<T, BM / 2, BN / 2, BK, AK, BKC, TAG + 2>(dr, alpha, A, Br, beta, Cr, s, Workspace{});
       return;
     }
    }
   }
   const int nkt = (d.K + BK - 1) / BK;
   const long total = (long)d.KB * nkt;
-  // split the reduction when the grid is too small to fill 256 CUs
-  int splitk = 1;
-  const long wgs = ntiles * nbatch;
-  if (wgs < 512 && total >= 8) {
-    long want = (1024 + wgs - 1) / wgs;
-    want = std::min<long>(want, total / 4);
-    const size_t per = (size_t)d.M * d.N * nbatch * sizeof(T);
-    if (per > 0) want = std::min<long>(want, (long)(ws.bytes / per));
-    want = std::min<long>(want, 256);
-    if (want >= 2) splitk = (int)want;
+  const size_t per = (size_t)d.M * d.N * nbatch * sizeof(T);
+  int splitk = auto_splitk(ntiles * nbatch, total, per, ws.bytes);
+  if (d.splitk > 0) {
+    splitk = d.splitk;
+    if (splitk > 1 && (splitk > 256 || ws.bytes / per < (size_t)splitk))
+      throw InvalidArg("gemm: workspace too small for the requested reduction splits");
   }
   dim3 grid((unsigned)(ntiles * nbatch), (unsigned)splitk, 1);
   if (splitk == 1) {
@@ -699,7 +711,7 @@ void gemm_dispatch(const GemmDesc& d, T alpha, const T* A, const T* B, T beta, T
                    Workspace ws) {
   if (d.M <= 0 || d.N <= 0 || d.nb1 <= 0 || d.nb2 <= 0) return;
   if (d.K <= 0 || d.KB <= 0) throw InvalidArg("gemm: empty reduction");
-  const bool big = d.M >= 96 && d.N >= 96;
+  const bool big = d.M >= 96 && d.N >= 96 && d.tile != 64;
   const bool ak = d.transA == 0, bk = d.transB != 0;
 #define PPW_GEMM_CASE(BMv, BNv, AKv, BKv)                                           \
   if (ak == AKv && bk == BKv) {                                                     \
@@ -783,7 +795,12 @@ int gemm_group_impl(const std::vector<GemmCall<T>>& calls, hipStream_t s) {
     const GemmDesc& d = c.d;
     if (d.M <= 0 || d.N <= 0 || d.nb1 <= 0 || d.nb2 <= 0) continue;
     if (d.K <= 0 || d.KB <= 0) throw InvalidArg("gemm: empty reduction");
-    const Key k{d.M >= 96 && d.N >= 96, d.transA == 0, d.transB != 0, c.tag};
+    if (d.splitk > 1) {
+      // fixed reduction splits need the split-K launch
+      single_dispatch(c, s);
+      continue;
+    }
+    const Key k{d.M >= 96 && d.N >= 96 && d.tile != 64, d.transA == 0, d.transB != 0, c.tag};
     size_t i = 0;
     while (i < keys.size() && !(keys[i] == k)) ++i;
     if (i == keys.size()) {
@@ -815,6 +832,17 @@ int gemm_group_impl(const std::vector<GemmCall<T>>& calls, hipStream_t s) {
 }
 
 }  // namespace
+
+int gemm_auto_splitk(const GemmDesc& d, size_t ws_bytes, bool fp32) {
+  if (d.splitk > 0) return d.splitk;
+  const bool big = d.M >= 96 && d.N >= 96 && d.tile != 64;
+  const int BM = big ? 128 : 64, BN = BM;
+  const long ntiles = (long)((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN);
+  const long nbatch = (long)d.nb1 * d.nb2;
+  const long total = (long)d.KB * ((d.K + 15) / 16);
+  const size_t per = (size_t)d.M * d.N * nbatch * (fp32 ? sizeof(float) : sizeof(double));
+  return auto_splitk(ntiles * nbatch, total, per, ws_bytes);
+}
 
 int gemm_group_f64(const std::vector<GemmCall<double>>& calls, hipStream_t s) { return gemm_group_impl(calls, s); }
 int gemm_group_f32(const std::vector<GemmCall<float>>& calls, hipStream_t s) { return gemm_group_impl(calls, s); }

@@ -474,26 +474,38 @@ void contract(Context& c, const Ops<T>& t, Emit<T>& e, int order, int k, const T
     d.sC1 = N;
     e.gemm(d, mone, t.Boo, t.G, zero, AV, c.ws);
   }
-  // U[(q,j)][(s,P,i)] = sum_b V[(q,j)][b] BovLam[(s,P,i)][b];  BV = -sum U R
+  // U[(q,j)][(s,P,i)] = sum_b V[(q,j)][b] BovLam[(s,P,i)][b], stored as [j][(s,P)][q][i]
+  // (row (q,j) of the product at q o + j Ucols k, column ((s,P),i) at (s,P) k o + i) so
+  // that BV = -sum U R reads it with uniform rows (q,i)
   const int ns = order >= 2 ? 2 : 1;
   {
     const long Ucols = (long)ns * X * o;
-    e.gemm(gd(k * o, (int)Ucols, v, 0, v, 1, v, Ucols), one, V, t.BovLam, zero, t.U, c.ws);
+    {
+      GemmDesc d = gd(k * o, (int)Ucols, v, 0, v, 1, v, Ucols * k);
+      d.cRm = o;
+      d.cSm = o;
+      d.cRn = o;
+      d.cSn = (long)k * o;
+      e.gemm(d, one, V, t.BovLam, zero, t.U, c.ws);
+    }
     if (ns == c.ns) {
-      GemmDesc d = gd(o, v, o * ns * X, 1, o, 0, v, v);
-      d.nb1 = k;
-      d.sA1 = (long)o * Ucols;
-      d.sC1 = N;
+      // one GEMM over rows (q,i), with the reduction splits the same product batched
+      // over q would take (identical sums and rounding)
+      GemmDesc bq = gd(o, v, o * ns * X, 1, o, 0, v, v);
+      bq.nb1 = k;
+      GemmDesc d = gd(k * o, v, o * ns * X, 1, (long)k * o, 0, v, v);
+      d.tile = 64;
+      d.splitk = gemm_auto_splitk(bq, c.ws.bytes, sizeof(T) == sizeof(float));
       e.gemm(d, mone, t.U, t.R, zero, BV, c.ws);
     } else {
-      // first-order product on a second-order handle: K_B(V) = sum_(j,P) U[q][(j,P)][i] Bov[P][j][a],
+      // first-order product on a second-order handle: K_B(V) = sum_(j,P) U[j][P][q][i] Bov[P][j][a],
       // with R[j][1][P][a] = Bov[P][j][a] (outer loop over j, inner P)
-      GemmDesc d = gd(o, v, X, 1, o, 0, v, v);
+      GemmDesc d = gd(o, v, X, 1, (long)k * o, 0, v, v);
       d.KB = o;
-      d.sAk = (long)X * o;
+      d.sAk = Ucols * k;
       d.sBk = (long)c.ns * X * v;
       d.nb1 = k;
-      d.sA1 = (long)o * Ucols;
+      d.sA1 = o;
       d.sC1 = N;
       e.gemm(d, mone, t.U, t.R + (size_t)X * v, zero, BV, c.ws);
     }
@@ -511,40 +523,48 @@ void contract(Context& c, const Ops<T>& t, Emit<T>& e, int order, int k, const T
     e.gemm(d, mone, t.Boo, V, one, t.G, c.ws);
   }
   const long kX = (long)k * X;
+  // H = tau G is written as [q][(i,c)][P] for the ib occupied rows i of the strip (the
+  // C index split sends column (q,P) of the product to q ib v X + P), so that both outputs
+  // read it with uniform strides.
   auto outputs = [&](const T* H, int i0, int ib) {
-    // BV[q][i][a] += sum_(c,P) H[(i,c)][(q,P)] Bvv[P][c][a]    rows i0..i0+ib-1; the row
-    // stride of H is v k X, so the rows go in chunks whose in-tile offsets fit 32 bits
+    const long hq = (long)ib * v * X;
+    // BV[q][i][a] += sum_(c,P) H[q][(i,c)][P] Bvv[P][c][a]: one GEMM with rows (q,i),
+    // written at q N + (i0 + i) v.  Its reduction splits are those the same product
+    // batched over q would take, so every element is summed and rounded alike.
     {
-      const long lda = (long)v * kX;
-      const int rchunk = (int)std::max<long>(1, std::min<long>(ib, (2147483647L - 64) / lda - 1));
-      for (int r0 = 0; r0 < ib; r0 += rchunk) {
-        const int rn = std::min(rchunk, ib - r0);
-        GemmDesc d = gd(rn, v, X, 0, lda, 0, (long)v * v, v);
-        d.KB = v;
-        d.sAk = kX;
-        d.sBk = v;
-        d.nb1 = k;
-        d.sA1 = X;
-        d.sC1 = N;
-        e.gemm(d, one, H + (size_t)r0 * lda, t.Bvv, one, BV + (size_t)(i0 + r0) * v, c.ws);
-      }
+      GemmDesc bq = gd(ib, v, X, 0, (long)v * X, 0, (long)v * v, v);
+      bq.KB = v;
+      bq.sAk = X;
+      bq.sBk = v;
+      bq.nb1 = k;
+      GemmDesc d = gd(k * ib, v, X, 0, (long)v * X, 0, (long)v * v, v);
+      d.KB = v;
+      d.sAk = X;
+      d.sBk = v;
+      d.cRm = ib;
+      d.cSm = N;
+      d.tile = 64;
+      d.splitk = gemm_auto_splitk(bq, c.ws.bytes, sizeof(T) == sizeof(float));
+      e.gemm(d, one, H, t.Bvv, one, BV + (size_t)i0 * v, c.ws);
     }
-    // BV[q][i][a] -= sum_(kk,P) Boo[P][i][kk] H[(kk,a)][(q,P)]   kk in i0..i0+ib-1
+    // BV[q][i][a] -= sum_(kk,P) Boo[P][i][kk] H[q][(kk,a)][P]   kk in i0..i0+ib-1
     {
-      GemmDesc d = gd(o, v, X, 0, (long)o * X, 1, kX, v);
+      GemmDesc d = gd(o, v, X, 0, (long)o * X, 1, X, v);
       d.KB = ib;
       d.sAk = X;
-      d.sBk = (long)v * kX;
+      d.sBk = (long)v * X;
       d.nb1 = k;
-      d.sB1 = X;
+      d.sB1 = hq;
       d.sC1 = N;
       e.gemm(d, mone, t.Boo_t + (size_t)i0 * X, H, one, BV, c.ws);
     }
   };
   double hflops = 0.0;
   if (t.tau) {
-    // H[(i,c)][(q,P)] = sum_(j,d) tau[(i,c)][(j,d)] G[(q,P)][(j,d)]
-    GemmDesc d = gd((int)N, (int)kX, (int)N, 0, N, 1, N, kX);
+    // H[q][(i,c)][P] = sum_(j,d) tau[(i,c)][(j,d)] G[(q,P)][(j,d)]
+    GemmDesc d = gd((int)N, (int)kX, (int)N, 0, N, 1, N, X);
+    d.cRn = X;
+    d.cSn = N * X;
     const int ev = e.tape ? -1 : c.events.start(s);
     e.gemm(d, one, t.tau, t.G, zero, t.H, c.ws, 1);
     if (ev >= 0) c.events.stop(ev, s, 1);
@@ -562,7 +582,9 @@ void contract(Context& c, const Ops<T>& t, Emit<T>& e, int order, int k, const T
         const double *eo = c.eps_o, *evv = c.eps_v;
         e.call([=](hipStream_t st) { tau_strip_t(Sst, o, v, i0, nb, eo, evv, tw, st); });
       }
-      GemmDesc d = gd(nb * v, (int)kX, (int)N, 0, N, 1, N, kX);
+      GemmDesc d = gd(nb * v, (int)kX, (int)N, 0, N, 1, N, X);
+      d.cRn = X;
+      d.cSn = (long)nb * v * X;
       const int ev = e.tape ? -1 : c.events.start(s);
       e.gemm(d, one, t.tau_w, t.G, zero, t.H, c.ws, 1);
       if (ev >= 0) c.events.stop(ev, s, 1);

@@ -170,6 +170,33 @@ def test_gemm_cmap(B, fp32, case):
 
 
 @pytest.mark.parametrize("fp32", [False, True])
+def test_gemm_cmap_peeled(B, fp32):
+    """Column-split output on a GEMM large enough for the peeled 64 x 64 tail (32 x 34
+    tiles of 128): the product lands at the mapped places, and equals bit for bit the
+    same GEMM written plainly (both tiles shapes accumulate every element over the same
+    k sequence), the amplitude contraction's layout [q][(i,c)][P]."""
+    rng = np.random.default_rng(9)
+    M, N, K, R = 4096, 128 * 33 + 40, 40, 600
+    nblk = (N + R - 1) // R
+    A = rng.standard_normal((M, K))
+    Bt = rng.standard_normal((N, K))
+    dt = torch.float32 if fp32 else torch.float64
+    dA, dB = (torch.tensor(x, dtype=dt, device="cuda") for x in (A, Bt))
+    dC = torch.full((nblk * M * R,), 7.0, dtype=dt, device="cuda")
+    B.gemm_cmap(dA, dB, dC, M=M, N=N, K=K, transA=0, lda=K, transB=1, ldb=K, ldc=R, cRn=R, cSn=M * R, fp32=fp32)
+    dP = torch.empty((M, N), dtype=dt, device="cuda")
+    B.gemm(dA, dB, dP, M=M, N=N, K=K, transA=0, lda=K, transB=1, ldb=K, ldc=N, fp32=fp32)
+    off = torch.tensor(_cmap_offsets(M, N, R, 0, 0, R, M * R), device="cuda")
+    assert torch.equal(dC[off], dP)
+    ref = A @ Bt.T
+    tol = (2e-5 if fp32 else 1e-13) * np.sqrt(K) * 3
+    np.testing.assert_allclose(dP.double().cpu().numpy(), ref, rtol=(2e-5 if fp32 else 0), atol=tol)
+    untouched = torch.ones(nblk * M * R, dtype=torch.bool, device="cuda")
+    untouched[off.reshape(-1)] = False
+    assert bool((dC[untouched] == 7.0).all())
+
+
+@pytest.mark.parametrize("fp32", [False, True])
 def test_gemm_long_rows(B, fp32):
     """A k-contiguous left operand with few rows and a row stride of 2^28 + 64 elements
     (the layout of the amplitude strip against the B^vv factors at large sizes): a 128-row
