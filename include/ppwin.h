@@ -72,6 +72,7 @@ typedef enum {
 /* pp_sigma flags */
 #define PP_APPLY_METRIC 1u  /* return Sigma X instead of M X */
 #define PP_DEVICE_PTRS 2u   /* X and out are device pointers */
+#define PP_ASYNC 4u         /* return once the product is enqueued (with PP_DEVICE_PTRS only) */
 
 typedef struct pp_handle pp_handle;
 
@@ -147,9 +148,18 @@ void pp_default_options(pp_options* opt);
 pp_status pp_setup(const pp_system* sys, const pp_options* opt, pp_handle** out);
 
 /* out = M X (or Sigma X with PP_APPLY_METRIC) for m 2N-vectors.  X and out are
- * [m][2][n_occ][n_vir]; order (0..2) must not exceed the setup order.
- * Synchronous.  The same precision as the handle's FP64 path is used. */
+ * [m][2][n_occ][n_vir]; order (0..2) must not exceed the setup order.  The
+ * handle's FP64 path is used.  Synchronous, unless PP_ASYNC (which needs
+ * PP_DEVICE_PTRS): the call then returns once the work is enqueued on the
+ * handle's stream (opt->stream, or the stream the handle owns).  X must stay
+ * unchanged and out unread until that work is done: work the caller orders after
+ * it on opt->stream, pp_sync, or any later call on the handle (each waits for it
+ * first).  Asynchronous calls keep their staging buffers (4 * 2m * N doubles for
+ * the largest m so far) in the handle until pp_destroy. */
 pp_status pp_sigma(pp_handle* h, int32_t order, int32_t m, const double* X, double* out, uint32_t flags);
+
+/* Waits until every product enqueued on the handle with PP_ASYNC is done. */
+pp_status pp_sync(pp_handle* h);
 
 /* Roots of M z = omega Sigma z nearest omega0 on the positive branch, at the
  * handle's setup order: energies[n_roots] ascending (Ha); vectors

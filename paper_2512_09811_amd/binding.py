@@ -21,6 +21,7 @@ PP_FP64, PP_FP32 = 0, 1
 PP_FOLDED, PP_RIESZ = 0, 1
 PP_APPLY_METRIC = 1
 PP_DEVICE_PTRS = 2
+PP_ASYNC = 4
 PP_MAX_ROOTS = 64
 
 
@@ -116,6 +117,8 @@ def lib() -> C.CDLL:
         L.pp_mp2_energy.restype = dbl
         L.pp_device_bytes.argtypes = [vp]
         L.pp_device_bytes.restype = u64
+        L.pp_sync.argtypes = [vp]
+        L.pp_sync.restype = C.c_int
         L.pp_destroy.argtypes = [vp]
         L.pp_destroy.restype = C.c_int
         L.pp_status_string.argtypes = [C.c_int]
@@ -248,12 +251,17 @@ class Handle:
         _check(st, self.h)
         return out
 
-    def sigma_device(self, X, out, order: Optional[int] = None, metric: bool = False):
-        """Same as sigma() on torch device tensors (no host copies)."""
+    def sigma_device(self, X, out, order: Optional[int] = None, metric: bool = False, async_: bool = False):
+        """Same as sigma() on torch device tensors (no host copies).  async_=True returns
+        once the product is enqueued on the handle's stream (see sync())."""
         m = X.shape[0]
-        flags = PP_DEVICE_PTRS | (PP_APPLY_METRIC if metric else 0)
+        flags = PP_DEVICE_PTRS | (PP_APPLY_METRIC if metric else 0) | (PP_ASYNC if async_ else 0)
         st = lib().pp_sigma(self.h, self.order if order is None else order, m, X.data_ptr(), out.data_ptr(), flags)
         _check(st, self.h)
+
+    def sync(self):
+        """Waits for the products enqueued with async_=True."""
+        _check(lib().pp_sync(self.h), self.h)
 
     def products(self, V, AV, BV, SV=None, order: Optional[int] = None, fp32: bool = False):
         """A V, B V, S V for torch device tensors [k][N] (internal test hook)."""

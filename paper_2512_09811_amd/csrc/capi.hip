@@ -17,6 +17,10 @@ struct pp_handle {
   ppw::Context* ctx = nullptr;
   pp_options opt{};
   std::string err;
+  // staging buffers of asynchronous products (V, AV, BV, SV), kept until pp_destroy
+  double* abuf = nullptr;
+  size_t acap = 0;     // doubles per buffer
+  bool pending = false;  // asynchronous work may still be running on the handle's stream
 };
 
 namespace {
@@ -24,6 +28,18 @@ namespace {
 thread_local std::string g_setup_error;
 using ppw::guarded;
 
+}  // namespace
+
+namespace {
+// Waits for asynchronous products still running on the handle's stream, so that the
+// caller's next call (whatever streams it uses) finds their buffers settled.
+void settle(pp_handle* h) {
+  if (h->pending) {
+    PPW_HIP(hipSetDevice(h->ctx->device));
+    PPW_HIP(hipStreamSynchronize(h->ctx->stream));
+    h->pending = false;
+  }
+}
 }  // namespace
 
 extern "C" {
@@ -106,20 +122,48 @@ pp_status pp_sigma(pp_handle* h, int32_t order, int32_t m, const double* X, doub
     PPW_HIP(hipSetDevice(c.device));
     const long N = c.N;
     const bool dev = (flags & PP_DEVICE_PTRS) != 0;
+    const bool async = (flags & PP_ASYNC) != 0;
+    if (async && !dev) throw ppw::InvalidArg("PP_ASYNC needs PP_DEVICE_PTRS");
     const int k = 2 * m;
-    double* V = c.arena.alloc<double>((size_t)k * N, "sigma V");
-    double* AV = c.arena.alloc<double>((size_t)k * N, "sigma AV");
-    double* BV = c.arena.alloc<double>((size_t)k * N, "sigma BV");
-    double* SV = c.arena.alloc<double>((size_t)k * N, "sigma SV");
-    double* out = dev ? outp : c.arena.alloc<double>((size_t)2 * m * N, "sigma out");
+    const size_t per = (size_t)k * N;
     struct Free {
       ppw::Context& c;
       std::vector<void*> p;
       ~Free() {
         for (void* q : p) c.arena.free(q);
       }
-    } fr{c, {V, AV, BV, SV}};
-    if (!dev) fr.p.push_back(out);
+    } fr{c, {}};
+    double *V, *AV, *BV, *SV;
+    if (async) {
+      // handle-owned staging, grown only after earlier asynchronous work is done
+      if (per > h->acap) {
+        settle(h);
+        if (h->abuf) c.arena.free(h->abuf);
+        h->abuf = nullptr;
+        h->acap = 0;
+        h->abuf = c.arena.alloc<double>(4 * per, "async sigma staging");
+        h->acap = per;
+      }
+      V = h->abuf;
+      AV = V + h->acap;
+      BV = AV + h->acap;
+      SV = BV + h->acap;
+    } else {
+      settle(h);
+      V = c.arena.alloc<double>(per, "sigma V");
+      fr.p.push_back(V);
+      AV = c.arena.alloc<double>(per, "sigma AV");
+      fr.p.push_back(AV);
+      BV = c.arena.alloc<double>(per, "sigma BV");
+      fr.p.push_back(BV);
+      SV = c.arena.alloc<double>(per, "sigma SV");
+      fr.p.push_back(SV);
+    }
+    double* out = outp;
+    if (!dev) {
+      out = c.arena.alloc<double>((size_t)2 * m * N, "sigma out");
+      fr.p.push_back(out);
+    }
     const hipMemcpyKind kin = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     PPW_HIP(hipMemcpy2DAsync(V, N * sizeof(double), X, 2 * N * sizeof(double), N * sizeof(double), m, kin,
                              c.stream));
@@ -130,7 +174,20 @@ pp_status pp_sigma(pp_handle* h, int32_t order, int32_t m, const double* X, doub
     ppw::combine_pairs(N, m, AV, BV, SV, metric, out, c.stream);
     if (!dev)
       PPW_HIP(hipMemcpyAsync(outp, out, sizeof(double) * 2 * m * N, hipMemcpyDeviceToHost, c.stream));
+    if (async) {
+      h->pending = true;
+      return;
+    }
     PPW_HIP(hipStreamSynchronize(c.stream));
+  });
+}
+
+pp_status pp_sync(pp_handle* h) {
+  if (!h || !h->ctx) return PP_EINVAL;
+  return guarded(&h->err, [&] {
+    PPW_HIP(hipSetDevice(h->ctx->device));
+    h->pending = true;  // also waits for anything else on the stream
+    settle(h);
   });
 }
 
@@ -144,6 +201,7 @@ pp_status pp_window_solve(pp_handle* h, double omega0, int32_t n_roots, double* 
     if (!energies) throw ppw::InvalidArg("energies must not be NULL");
     if (osc && !h->ctx->dip) throw ppw::InvalidArg("oscillator strengths need dipole integrals at setup");
     const ppw::SolveOptions so = ppw::solve_options(h->opt);
+    settle(h);
     ppw::window_solve(*h->ctx, so, omega0, n_roots, energies, vectors, osc, info);
   });
 }
@@ -159,6 +217,7 @@ pp_status pp_window_solve_batch(pp_handle* h, int32_t n_windows, const double* o
     if (n_roots < 1 || n_roots > PP_MAX_ROOTS || n_roots > h->ctx->N) throw ppw::InvalidArg("n_roots out of range");
     if (osc && !h->ctx->dip) throw ppw::InvalidArg("oscillator strengths need dipole integrals at setup");
     const ppw::SolveOptions so = ppw::solve_options(h->opt);
+    settle(h);
     ppw::window_solve_many(*h->ctx, so, n_windows, omega0, n_roots, energies, vectors, osc, info);
   });
 }
@@ -167,6 +226,7 @@ pp_status pp_get_stats(pp_handle* h, pp_stats* st) {
   if (!h || !h->ctx || !st) return PP_EINVAL;
   return guarded(&h->err, [&] {
     PPW_HIP(hipSetDevice(h->ctx->device));
+    settle(h);
     h->ctx->resolve_stats();
     const ppw::SigmaStats& s = h->ctx->stats;
     st->product_flops = s.flops;
@@ -181,6 +241,7 @@ pp_status pp_get_stats(pp_handle* h, pp_stats* st) {
 pp_status pp_reset_stats(pp_handle* h) {
   if (!h || !h->ctx) return PP_EINVAL;
   return guarded(&h->err, [&] {
+    settle(h);
     h->ctx->resolve_stats();
     h->ctx->stats = ppw::SigmaStats{};
   });
@@ -194,7 +255,12 @@ pp_status pp_destroy(pp_handle* h) {
   if (!h) return PP_OK;
   std::string dummy;
   pp_status st = guarded(&dummy, [&] {
-    if (h->ctx) (void)hipSetDevice(h->ctx->device);
+    if (h->ctx) {
+      (void)hipSetDevice(h->ctx->device);
+      settle(h);
+      if (h->abuf) h->ctx->arena.free(h->abuf);
+      h->abuf = nullptr;
+    }
     delete h->ctx;
     h->ctx = nullptr;
   });
@@ -205,6 +271,7 @@ pp_status pp_destroy(pp_handle* h) {
 pp_status pp_exciton_dos(pp_handle* h, int32_t n_bins, const double* edges, double* counts, double* mu2) {
   if (!h || !h->ctx) return PP_EINVAL;
   return guarded(&h->err, [&] {
+    settle(h);
     if (n_bins < 1 || n_bins > (1 << 20)) throw ppw::InvalidArg("n_bins out of range");
     if (!edges || !counts) throw ppw::InvalidArg("edges and counts must not be NULL");
     for (int b = 0; b < n_bins; ++b)
@@ -432,6 +499,7 @@ pp_status ppint_riesz_filter(pp_handle* h, double center, double radius, int32_t
                              int32_t m, const double* V, double* out, int32_t* iters, double* worst) {
   if (!h || !h->ctx) return PP_EINVAL;
   return guarded(&h->err, [&] {
+    settle(h);
     ppw::Context& c = *h->ctx;
     if (m < 1 || m > 64) throw ppw::InvalidArg("m must be in 1..64");
     if (nodes < 1 || nodes > 32) throw ppw::InvalidArg("nodes must be in 1..32");
@@ -476,6 +544,7 @@ pp_status ppint_products(pp_handle* h, int32_t order, int32_t k, const double* V
                          int32_t fp32) {
   if (!h || !h->ctx) return PP_EINVAL;
   return guarded(&h->err, [&] {
+    settle(h);
     if (order < 0 || order > h->ctx->order) throw ppw::InvalidArg("order exceeds the setup order");
     if (fp32)
       ppw::sigma_core_f32(*h->ctx, order, k, V, AV, BV, SV);

@@ -69,6 +69,42 @@ def test_sigma_order1_handle(P):
     np.testing.assert_allclose(got, dense.sigma_dense(sys, 1, X), rtol=0, atol=1e-13)
 
 
+def test_sigma_async(P):
+    """PP_ASYNC products against the oracle: on the caller's stream they are read in
+    stream order (two calls in a row, the second larger so the handle's staging grows);
+    on the handle's own stream they are settled by sync() or by the next call on the
+    handle; host pointers are refused."""
+    import torch
+    sys = _sys("mid")
+    X, X2 = random_block(5, sys.N, 4), random_block(6, sys.N, 7)
+    ref, ref2 = dense.sigma_dense(sys, 2, X), dense.sigma_dense(sys, 2, X2)
+    tol = 1e-12 * max(np.abs(ref).max(), np.abs(ref2).max())
+    s = torch.cuda.Stream()
+    with P.Handle.from_system(sys, order=2, stream=s.cuda_stream) as h:
+        with torch.cuda.stream(s):
+            dX, dX2 = torch.tensor(X, device="cuda"), torch.tensor(X2, device="cuda")
+            out, out2 = torch.empty_like(dX), torch.empty_like(dX2)
+            h.sigma_device(dX, out, async_=True)
+            h.sigma_device(dX2, out2, async_=True)
+            got, got2 = out.cpu().numpy(), out2.cpu().numpy()
+        np.testing.assert_allclose(got, ref, rtol=0, atol=tol)
+        np.testing.assert_allclose(got2, ref2, rtol=0, atol=tol)
+    with P.Handle.from_system(sys, order=2) as h:
+        dX = torch.tensor(X, device="cuda")
+        torch.cuda.synchronize()
+        out, out2 = torch.empty_like(dX), torch.empty_like(dX)
+        h.sigma_device(dX, out, async_=True)
+        h.sync()
+        np.testing.assert_allclose(out.cpu().numpy(), ref, rtol=0, atol=tol)
+        h.sigma_device(dX, out2, async_=True)
+        host = h.sigma(X)  # a synchronous call waits for the pending product first
+        np.testing.assert_allclose(out2.cpu().numpy(), ref, rtol=0, atol=tol)
+        np.testing.assert_allclose(host, ref, rtol=0, atol=tol)
+        hout = np.empty_like(X)
+        st = P.lib().pp_sigma(h.h, 2, X.shape[0], X.ctypes.data, hout.ctypes.data, P.PP_ASYNC)
+        assert st == P.PP_EINVAL
+
+
 def _check_window(sys, order, omega0, nr, e, vec, f, info):
     A, B, S = dense.assemble(sys, order)
     e_ref, X_ref, Y_ref, f_ref = pencil.window_solve(A, B, S, sys.dip, omega0, nr)
