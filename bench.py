@@ -272,8 +272,8 @@ def serve_main(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is a design "
-                                   "note, not implemented)"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
+                                   "described but not implemented)"}))
         sys.exit(2)
     if args.riesz:
         riesz_main(args)

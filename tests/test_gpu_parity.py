@@ -4,7 +4,7 @@ Products (pp_sigma) at orders 0-2 are compared element by element with the
 dense oracle on seeded systems that span several GEMM tiles and ragged tails;
 window solves are compared root by root with the oracle's exact pencil
 solution.  Tolerances: products 1e-12 relative to the largest element (FP64
-throughout); energies 1e-8 Ha (the spec bar is 1e-6 Ha; the FP64 solver
+throughout); energies 1e-8 Ha (the target accuracy is 1e-6 Ha; the FP64 solver
 converges residuals to 1e-9); oscillator strengths 1e-5 relative above
 1e-4 max(f), 1e-9 absolute below.
 """
