@@ -56,7 +56,10 @@ typedef enum {
 
 typedef enum {
   PP_FP64 = 0,       /* every contraction in FP64 on FP64 matrix cores */
-  PP_FP32 = 1        /* subspace products in FP32 matrix cores, FP64 residual refinement */
+  PP_FP32 = 1,       /* subspace products in FP32 matrix cores, FP64 residual refinement */
+  PP_SPLIT_BF16 = 2  /* as PP_FP32, with the amplitude contraction as split-BF16 products: each
+                        FP32 operand split into two BF16 parts, three BF16 MFMA products with FP32
+                        accumulation (relative error about 2^-16); FP64 residual refinement */
 } pp_precision;
 
 /* How a window solve isolates the roots near omega0 (pp_options.method). */

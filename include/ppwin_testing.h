@@ -20,14 +20,16 @@ extern "C" {
 /* C[b](m,n) = alpha * sum_kb sum_k A(m,k) B(k,n) + beta * C, the library GEMM
  * (layouts as in the library: transA = 0 -> A[m*lda+k], 1 -> A[k*lda+m]; transB = 0
  * -> B[k*ldb+n], 1 -> B[n*ldb+k]; batch b offsets b*sA, b*sB, b*sC; outer reduction
- * kb offsets kb*sAk, kb*sBk).  fp32 != 0 runs the FP32 matrix-core kernel on
- * float arrays.  ws_bytes of scratch are allocated for split-K (0 = no split). */
+ * kb offsets kb*sAk, kb*sBk).  fp32 = 1 runs the FP32 matrix-core kernel on float
+ * arrays, fp32 = 2 the split-BF16 kernel on float arrays (transA = 0, transB = 1, no
+ * batch or outer reduction, else PP_EINVAL).  ws_bytes of scratch are allocated for
+ * split-K (0 = no split). */
 pp_status ppint_gemm(int32_t fp32, int32_t M, int32_t N, int32_t K, int32_t KB, int32_t nbatch, int32_t transA,
                      int64_t lda, int64_t sA, int64_t sAk, int32_t transB, int64_t ldb, int64_t sB, int64_t sBk,
                      int64_t ldc, int64_t sC, double alpha, const void* A, const void* B, double beta, void* C,
                      uint64_t ws_bytes);
 
-/* ppint_gemm without batches or outer reduction, with C rows and columns split into
+/* ppint_gemm (fp32 as there) without batches or outer reduction, with C rows and columns split into
  * index pairs: C(m,n) = C[(m / cRm) * cSm + (m % cRm) * ldc + (n / cRn) * cSn + n % cRn]
  * (cRm = 0: m * ldc; cRn = 0: n).  Errors: PP_EINVAL for a negative split or a
  * shape the kernel cannot address. */

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libppwin.so")
 
 PP_OK, PP_EINVAL, PP_ENOMEM, PP_ENOTCONV, PP_EUNSTABLE, PP_EDEVICE, PP_ENOTSUP, PP_EPENDING = range(8)
-PP_FP64, PP_FP32 = 0, 1
+PP_FP64, PP_FP32, PP_SPLIT_BF16 = 0, 1, 2
 PP_FOLDED, PP_RIESZ = 0, 1
 PP_APPLY_METRIC = 1
 PP_DEVICE_PTRS = 2
@@ -351,7 +351,7 @@ class Handle:
 def gemm(A, B, C_, *, M, N, K, KB=1, nbatch=1, transA=0, lda, sA=0, sAk=0, transB=0, ldb, sB=0, sBk=0, ldc,
          sC=0, alpha=1.0, beta=0.0, ws_bytes=0, fp32=False):
     """Library GEMM on torch device tensors (internal test hook)."""
-    st = lib().ppint_gemm(1 if fp32 else 0, M, N, K, KB, nbatch, transA, lda, sA, sAk, transB, ldb, sB, sBk, ldc, sC,
+    st = lib().ppint_gemm(int(fp32), M, N, K, KB, nbatch, transA, lda, sA, sAk, transB, ldb, sB, sBk, ldc, sC,
                           alpha, A.data_ptr(), B.data_ptr(), beta, C_.data_ptr(), ws_bytes)
     _check(st)
 
@@ -359,7 +359,7 @@ def gemm(A, B, C_, *, M, N, K, KB=1, nbatch=1, transA=0, lda, sA=0, sAk=0, trans
 def gemm_cmap(A, B, C_, *, M, N, K, transA=0, lda, transB=0, ldb, ldc, cRm=0, cSm=0, cRn=0, cSn=0, alpha=1.0,
               beta=0.0, ws_bytes=0, fp32=False):
     """Library GEMM with C rows/columns split into index pairs (internal test hook)."""
-    st = lib().ppint_gemm_cmap(1 if fp32 else 0, M, N, K, transA, lda, transB, ldb, ldc, cRm, cSm, cRn, cSn, alpha,
+    st = lib().ppint_gemm_cmap(int(fp32), M, N, K, transA, lda, transB, ldb, ldc, cRm, cSm, cRn, cSn, alpha,
                                A.data_ptr(), B.data_ptr(), beta, C_.data_ptr(), ws_bytes)
     _check(st)
 

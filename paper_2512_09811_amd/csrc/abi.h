@@ -65,7 +65,8 @@ inline void check_host_system(const pp_system& sys) {
 }
 
 inline void check_options(const pp_options& opt) {
-  if (opt.precision != PP_FP64 && opt.precision != PP_FP32) throw InvalidArg("unknown precision");
+  if (opt.precision != PP_FP64 && opt.precision != PP_FP32 && opt.precision != PP_SPLIT_BF16)
+    throw InvalidArg("unknown precision");
   if (opt.max_basis > 512) throw InvalidArg("max_basis must be <= 512");
   if (!(opt.tol > 0)) throw InvalidArg("tol must be positive");
   if (opt.method != PP_FOLDED && opt.method != PP_RIESZ) throw InvalidArg("unknown method");
@@ -78,7 +79,7 @@ inline void check_options(const pp_options& opt) {
 
 inline SolveOptions solve_options(const pp_options& o) {
   SolveOptions so;
-  so.precision = o.precision;
+  so.precision = o.precision == PP_FP64 ? 0 : 1;  // 1: reduced-precision products + FP64 refinement
   so.tol = o.tol;
   so.block = o.block;
   so.krylov_steps = o.krylov_steps;

@@ -93,7 +93,8 @@ pp_status pp_setup(const pp_system* sys, const pp_options* opt_in, pp_handle** o
     p.device_ptrs = sys->device_ptrs != 0;
     p.store_amplitudes = opt.store_amplitudes;
     p.strip_rows = opt.strip_rows;
-    p.want_f32 = opt.precision == PP_FP32;
+    p.want_f32 = opt.precision != PP_FP64;
+    p.split_bf16 = opt.precision == PP_SPLIT_BF16;
     p.tda = opt.tda != 0;
     p.budget = opt.hbm_budget;
     p.device = opt.device;
@@ -375,7 +376,9 @@ pp_status ppint_gemm(int32_t fp32, int32_t M, int32_t N, int32_t K, int32_t KB, 
       w.ptr = ws;
       w.bytes = ws_bytes;
     }
-    if (fp32)
+    if (fp32 == 2)
+      ppw::gemm_f32_sbf16(d, (float)alpha, (const float*)A, (const float*)B, (float)beta, (float*)C, nullptr);
+    else if (fp32)
       ppw::gemm_f32(d, (float)alpha, (const float*)A, (const float*)B, (float)beta, (float*)C, nullptr, w);
     else
       ppw::gemm_f64(d, alpha, (const double*)A, (const double*)B, beta, (double*)C, nullptr, w);
@@ -410,7 +413,9 @@ pp_status ppint_gemm_cmap(int32_t fp32, int32_t M, int32_t N, int32_t K, int32_t
       w.ptr = ws;
       w.bytes = ws_bytes;
     }
-    if (fp32)
+    if (fp32 == 2)
+      ppw::gemm_f32_sbf16(d, (float)alpha, (const float*)A, (const float*)B, (float)beta, (float*)C, nullptr);
+    else if (fp32)
       ppw::gemm_f32(d, (float)alpha, (const float*)A, (const float*)B, (float)beta, (float*)C, nullptr, w);
     else
       ppw::gemm_f64(d, alpha, (const double*)A, (const double*)B, beta, (double*)C, nullptr, w);

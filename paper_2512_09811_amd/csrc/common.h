@@ -91,6 +91,11 @@ void gemm_f32(const GemmDesc& d, float alpha, const float* A, const float* B, fl
 // Same kernels under a separate symbol, used for the amplitude contraction H = tau G.
 void gemm_f64_hhat(const GemmDesc& d, double alpha, const double* A, const double* B, double beta, double* C,
                    hipStream_t s, Workspace ws = {});
+// Split-BF16 product (three BF16 MFMAs per FP32 product, FP32 accumulation, relative
+// error about 2^-16): operands contiguous along k, no batch or outer reduction; C
+// index splits allowed.  Used for the amplitude contraction in PP_SPLIT_BF16 mode.
+void gemm_f32_sbf16(const GemmDesc& d, float alpha, const float* A, const float* B, float beta, float* C,
+                    hipStream_t s);
 void gemm_f32_hhat(const GemmDesc& d, float alpha, const float* A, const float* B, float beta, float* C,
                    hipStream_t s, Workspace ws = {});
 

@@ -73,6 +73,7 @@ struct SetupParams {
   int store_amplitudes = -1;  // -1 auto
   int strip_rows = 0;
   bool want_f32 = false;       // keep FP32 copies for the reduced-precision product path
+  bool split_bf16 = false;     // reduced-precision amplitude contraction as split-BF16 products
   bool tda = false;            // Tamm-Dancoff: B = 0
   size_t budget = 0;
   int device = 0;
@@ -176,6 +177,7 @@ struct Context {
   int strip_rows = 0;
   double emp2 = 0.0;
   bool tda = false;  // Tamm-Dancoff: every B product (and the B diagonal) is zero
+  bool split_bf16 = false;  // reduced-precision amplitude contraction on BF16 matrix cores
 
   // FP32 copies for the reduced-precision path (optional)
   float *Bov32 = nullptr, *Boo32 = nullptr, *Bvv32 = nullptr, *BovLam32 = nullptr, *Boo_t32 = nullptr,

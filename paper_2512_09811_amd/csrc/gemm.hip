@@ -771,6 +771,13 @@ void group_dispatch(bool big, bool ak, bool bk, const GemmCall<T>* const* calls,
 
 template <typename T>
 void single_dispatch(const GemmCall<T>& c, hipStream_t s) {
+  if (c.tag == 2) {
+    if constexpr (std::is_same<T, float>::value)
+      gemm_f32_sbf16(c.d, c.alpha, c.A, c.B, c.beta, c.C, s);
+    else
+      throw InvalidArg("split-BF16 products take FP32 operands");
+    return;
+  }
   if (c.tag == 1)
     gemm_dispatch<T, 1>(c.d, c.alpha, c.A, c.B, c.beta, c.C, s, c.ws);
   else
@@ -795,8 +802,8 @@ int gemm_group_impl(const std::vector<GemmCall<T>>& calls, hipStream_t s) {
     const GemmDesc& d = c.d;
     if (d.M <= 0 || d.N <= 0 || d.nb1 <= 0 || d.nb2 <= 0) continue;
     if (d.K <= 0 || d.KB <= 0) throw InvalidArg("gemm: empty reduction");
-    if (d.splitk > 1) {
-      // fixed reduction splits need the split-K launch
+    if (d.splitk > 1 || c.tag == 2) {
+      // fixed reduction splits need the split-K launch; split-BF16 has its own kernel
       single_dispatch(c, s);
       continue;
     }
@@ -831,6 +838,135 @@ int gemm_group_impl(const std::vector<GemmCall<T>>& calls, hipStream_t s) {
   return grouped;
 }
 
+// ---------------------------------------------------------------------------
+// FP32 product on BF16 matrix cores ("split BF16"): each FP32 operand x is split into
+// hi = bf16(x) (round to nearest even) and lo = bf16(x - hi), and a b is taken as
+// hi_a lo_b + lo_a hi_b + hi_a hi_b with FP32 accumulation; the dropped lo_a lo_b and the
+// rounding of lo leave a relative error of about 2^-16 per product.  Three 16x16x32 BF16
+// MFMAs per 16x16x32 block.  Operands contiguous along k (A [m][k], B [n][k]); 128 x 128
+// tiles of 2 x 2 wave64s; k tiles of 32 FP32 values staged in LDS (register prefetch)
+// with rows padded to 36 values, so the 16 rows of a fragment read fall on 16 different
+// groups of 4 banks.  Lane l reads row l % 16, k = 8 (l / 16) .. + 7 (the operand layout
+// of the 16x16x32 BF16 MFMA, checked on the device); results come in the FP32 MFMA layout.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+constexpr int kSbBK = 32, kSbLD = 36;
+
+__device__ __forceinline__ void split8(const float* p, bf16x8_t& hi, bf16x8_t& lo) {
+  const f32x4_t x0 = *reinterpret_cast<const f32x4_t*>(p);
+  const f32x4_t x1 = *reinterpret_cast<const f32x4_t*>(p + 4);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const __bf16 h0 = (__bf16)x0[t], h1 = (__bf16)x1[t];
+    hi[t] = h0;
+    hi[t + 4] = h1;
+    lo[t] = (__bf16)(x0[t] - (float)h0);
+    lo[t + 4] = (__bf16)(x1[t] - (float)h1);
+  }
+}
+
+__global__ __launch_bounds__(kThreads, 2) void gemm_sbf16_kernel(GemmDesc d, float alpha,
+                                                                 const float* __restrict__ A,
+                                                                 const float* __restrict__ B, float beta,
+                                                                 float* __restrict__ C) {
+  constexpr int BM = 128, BN = 128, WTM = 64, WTN = 64, TM = 4, TN = 4, PL = BM * kSbBK / 4 / kThreads;
+  __shared__ __attribute__((aligned(16))) float As[2][BM * kSbLD];
+  __shared__ __attribute__((aligned(16))) float Bs[2][BN * kSbLD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
+  const int tiles_m = (d.M + BM - 1) / BM, tiles_n = (d.N + BN - 1) / BN;
+  int tm, tn;
+  tile_coords((int)xcd_remap(blockIdx.x, (long)gridDim.x), tiles_m, tiles_n, tm, tn);
+  const int m0 = tm * BM, n0 = tn * BN;
+  const float* At = A + (long)m0 * d.lda;
+  const float* Bt = B + (long)n0 * d.ldb;
+  const int lda32 = (int)d.lda, ldb32 = (int)d.ldb;
+  const int mrem = d.M - m0, nrem = d.N - n0;
+  const bool vec_ok = mrem >= BM && nrem >= BN && (d.lda % 4) == 0 && (d.ldb % 4) == 0 &&
+                      ((uintptr_t)At % 16) == 0 && ((uintptr_t)Bt % 16) == 0;
+  // slot q = i * 256 + tid of a k tile: row q / 8, four k values from 4 (q % 8)
+  f32x4_t ra[PL], rb[PL];
+  auto load = [&](int k0) {
+    const int krem = d.K - k0;
+    if (vec_ok && krem >= kSbBK) {
+#pragma unroll
+      for (int i = 0; i < PL; ++i) {
+        const int q = i * kThreads + tid, r = q >> 3, k4 = 4 * (q & 7);
+        ra[i] = *reinterpret_cast<const f32x4_t*>(At + r * lda32 + k0 + k4);
+        rb[i] = *reinterpret_cast<const f32x4_t*>(Bt + r * ldb32 + k0 + k4);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < PL; ++i) {
+        const int q = i * kThreads + tid, r = q >> 3, k4 = 4 * (q & 7);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int kk = k4 + t;
+          ra[i][t] = (r < mrem && kk < krem) ? At[r * lda32 + k0 + kk] : 0.0f;
+          rb[i][t] = (r < nrem && kk < krem) ? Bt[r * ldb32 + k0 + kk] : 0.0f;
+        }
+      }
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < PL; ++i) {
+      const int q = i * kThreads + tid, r = q >> 3, k4 = 4 * (q & 7);
+      *reinterpret_cast<f32x4_t*>(&As[buf][r * kSbLD + k4]) = ra[i];
+      *reinterpret_cast<f32x4_t*>(&Bs[buf][r * kSbLD + k4]) = rb[i];
+    }
+  };
+  f32x4_t acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  const int nkt = (d.K + kSbBK - 1) / kSbBK;
+  load(0);
+  store(0);
+  __syncthreads();
+  const int kq = 8 * (lane >> 4);
+  int buf = 0;
+  for (int kt = 0; kt < nkt; ++kt) {
+    const bool more = kt + 1 < nkt;
+    if (more) load((kt + 1) * kSbBK);
+    bf16x8_t ah[TM], al[TM], bh[TN], bl[TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) split8(&As[buf][(wm * WTM + i * 16 + (lane & 15)) * kSbLD + kq], ah[i], al[i]);
+#pragma unroll
+    for (int j = 0; j < TN; ++j) split8(&Bs[buf][(wn * WTN + j * 16 + (lane & 15)) * kSbLD + kq], bh[j], bl[j]);
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+      }
+    if (more) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  if (d.cRm | d.cRn) {
+    store_mapped<float, f32x4_t, TM, TN, WTM, WTN>(d, alpha, beta, C, m0, n0, wm, wn, lane, acc);
+    return;
+  }
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * WTM + i * 16 + Mfma<float>::row(lane, r);
+        const int col = n0 + wn * WTN + j * 16 + (lane & 15);
+        if (row < d.M && col < d.N) {
+          float* cp = C + (long)row * d.ldc + col;
+          float out = alpha * acc[i][j][r];
+          if (beta != 0.0f) out += beta * (*cp);
+          *cp = out;
+        }
+      }
+}
+
 }  // namespace
 
 int gemm_auto_splitk(const GemmDesc& d, size_t ws_bytes, bool fp32) {
@@ -842,6 +978,17 @@ int gemm_auto_splitk(const GemmDesc& d, size_t ws_bytes, bool fp32) {
   const long total = (long)d.KB * ((d.K + 15) / 16);
   const size_t per = (size_t)d.M * d.N * nbatch * (fp32 ? sizeof(float) : sizeof(double));
   return auto_splitk(ntiles * nbatch, total, per, ws_bytes);
+}
+
+void gemm_f32_sbf16(const GemmDesc& d, float alpha, const float* A, const float* B, float beta, float* C,
+                    hipStream_t s) {
+  if (d.M <= 0 || d.N <= 0) return;
+  if (d.K <= 0) throw InvalidArg("gemm: empty reduction");
+  if (d.transA != 0 || d.transB == 0 || d.KB != 1 || d.nb1 != 1 || d.nb2 != 1)
+    throw InvalidArg("split-BF16 GEMM: operands contiguous along k, no batch or outer reduction");
+  const long wgs = checked_workgroups<128, 128, kSbBK>(d);
+  gemm_sbf16_kernel<<<dim3((unsigned)wgs), kThreads, 0, s>>>(d, alpha, A, B, beta, C);
+  PPW_LAUNCH_CHECK();
 }
 
 int gemm_group_f64(const std::vector<GemmCall<double>>& calls, hipStream_t s) { return gemm_group_impl(calls, s); }

@@ -216,7 +216,7 @@ class Server {
   // device bytes a request may hold, and the amplitude policy it gets
   void plan(Request& r) const {
     const size_t N = (size_t)r.o * r.v;
-    const bool f32 = opt_.precision == PP_FP32;
+    const bool f32 = opt_.precision != PP_FP64;
     const double tau_bytes = (double)N * N * (f32 ? 12.0 : 8.0);
     r.store = r.order >= 2 && (opt_.store_amplitudes == 1 ||
                                (opt_.store_amplitudes < 0 && tau_bytes <= (double)budget_ / 16.0));
@@ -402,7 +402,8 @@ class Server {
       p.dip = r->has_dip ? r->dip.data() : nullptr;
       p.store_amplitudes = r->store ? 1 : 0;
       p.strip_rows = r->strip_rows;
-      p.want_f32 = opt_.precision == PP_FP32;
+      p.want_f32 = opt_.precision != PP_FP64;
+      p.split_bf16 = opt_.precision == PP_SPLIT_BF16;
       p.tda = opt_.tda != 0;
       p.budget = r->bytes;
       p.device = opt_.device;
@@ -413,7 +414,7 @@ class Server {
       std::vector<double>().swap(r->Bvv);
       const int k = window_block_vectors(c->N, r->n_roots, so_);
       sigma_reserve(*c, k, 0);
-      if (opt_.precision == PP_FP32) sigma_reserve(*c, k, 1);
+      if (opt_.precision != PP_FP64) sigma_reserve(*c, k, 1);
       r->energies.assign(r->n_roots, 0.0);
       r->vectors.assign((size_t)r->n_roots * 2 * c->N, 0.0);
       if (r->has_dip) r->osc.assign(r->n_roots, 0.0);

@@ -105,6 +105,7 @@ Context* setup_context(const SetupParams& p) {
     c->v = p.v;
     c->naux = p.naux;
     c->order = p.order;
+    c->split_bf16 = p.split_bf16 && p.want_f32;
     c->N = (long)p.o * p.v;
     c->device = p.device;
     PPW_HIP(hipSetDevice(p.device));
@@ -344,6 +345,15 @@ void gemm_t<float>(const GemmDesc& d, float a, const float* A, const float* B, f
                    Workspace ws) {
   gemm_f32(d, a, A, B, b, C, s, ws);
 }
+// Split-BF16 amplitude contraction (FP32 operands only).
+inline void gemm_sbf16_t(const GemmDesc& d, float a, const float* A, const float* B, float b, float* C,
+                         hipStream_t s) {
+  gemm_f32_sbf16(d, a, A, B, b, C, s);
+}
+inline void gemm_sbf16_t(const GemmDesc&, double, const double*, const double*, double, double*, hipStream_t) {
+  throw InvalidArg("split-BF16 products take FP32 operands");
+}
+
 template <typename T>
 void gemm_hhat_t(const GemmDesc& d, T a, const T* A, const T* B, T b, T* C, hipStream_t s, Workspace ws);
 template <>
@@ -397,7 +407,9 @@ struct Emit {
   std::vector<Step>* tape = nullptr;
   void gemm(const GemmDesc& d, T a, const T* A, const T* B, T b, T* C, Workspace ws, int tag = 0) {
     if (!tape) {
-      if (tag == 1)
+      if (tag == 2)
+        gemm_sbf16_t(d, a, A, B, b, C, s);
+      else if (tag == 1)
         gemm_hhat_t<T>(d, a, A, B, b, C, s, ws);
       else
         gemm_t<T>(d, a, A, B, b, C, s, ws);
@@ -559,6 +571,8 @@ void contract(Context& c, const Ops<T>& t, Emit<T>& e, int order, int k, const T
       e.gemm(d, mone, t.Boo_t + (size_t)i0 * X, H, one, BV, c.ws);
     }
   };
+  // the amplitude contraction: its own kernel symbol, or split-BF16 products in that mode
+  const int hhat_tag = (sizeof(T) == sizeof(float) && c.split_bf16) ? 2 : 1;
   double hflops = 0.0;
   if (t.tau) {
     // H[q][(i,c)][P] = sum_(j,d) tau[(i,c)][(j,d)] G[(q,P)][(j,d)]
@@ -566,7 +580,7 @@ void contract(Context& c, const Ops<T>& t, Emit<T>& e, int order, int k, const T
     d.cRn = X;
     d.cSn = N * X;
     const int ev = e.tape ? -1 : c.events.start(s);
-    e.gemm(d, one, t.tau, t.G, zero, t.H, c.ws, 1);
+    e.gemm(d, one, t.tau, t.G, zero, t.H, c.ws, hhat_tag);
     if (ev >= 0) c.events.stop(ev, s, 1);
     hflops += gemm_flops(d);
     c.stats.hhat_launches += 1;
@@ -586,7 +600,7 @@ void contract(Context& c, const Ops<T>& t, Emit<T>& e, int order, int k, const T
       d.cRn = X;
       d.cSn = (long)nb * v * X;
       const int ev = e.tape ? -1 : c.events.start(s);
-      e.gemm(d, one, t.tau_w, t.G, zero, t.H, c.ws, 1);
+      e.gemm(d, one, t.tau_w, t.G, zero, t.H, c.ws, hhat_tag);
       if (ev >= 0) c.events.stop(ev, s, 1);
       hflops += gemm_flops(d);
       c.stats.hhat_launches += 1;

@@ -196,6 +196,36 @@ def test_gemm_cmap_peeled(B, fp32):
     assert bool((dC[untouched] == 7.0).all())
 
 
+@pytest.mark.parametrize("shape", [(300, 260, 100), (256, 384, 6400), (130, 4200, 64)])
+def test_gemm_split_bf16(B, shape):
+    """Split-BF16 GEMM (k-contiguous operands, the amplitude contraction's layout) against
+    the float64 product of the same FP32 inputs: the split leaves about 2^-17 of |a||b| per
+    product, so the error stays below 1e-5 sqrt(K) max|a| max|b|; ragged tiles in m, n and
+    k, alpha and beta applied; and with a column index split on the output."""
+    M, N, K = shape
+    rng = np.random.default_rng(M + N + K)
+    A = rng.standard_normal((M, K)).astype(np.float32)
+    Bt = rng.standard_normal((N, K)).astype(np.float32)
+    C0 = rng.standard_normal((M, N)).astype(np.float32)
+    ref = 1.5 * (A.astype(np.float64) @ Bt.astype(np.float64).T) + 0.5 * C0
+    dA, dB, dC = (torch.tensor(x, device="cuda") for x in (A, Bt, C0))
+    B.gemm(dA, dB, dC, M=M, N=N, K=K, transA=0, lda=K, transB=1, ldb=K, ldc=N, alpha=1.5, beta=0.5, fp32=2)
+    tol = 1e-5 * np.sqrt(K) * np.abs(A).max() * np.abs(Bt).max()
+    err = np.abs(dC.double().cpu().numpy() - ref).max()
+    assert err <= tol, (err, tol)
+    # the same product through the split-BF16 kernel's mapped epilogue: blocks of 64 columns
+    R = 64
+    nblk = (N + R - 1) // R
+    dM = torch.zeros(nblk * M * R, dtype=torch.float32, device="cuda")
+    B.gemm_cmap(dA, dB, dM, M=M, N=N, K=K, transA=0, lda=K, transB=1, ldb=K, ldc=R, cRn=R, cSn=M * R, fp32=2)
+    dP = torch.zeros((M, N), dtype=torch.float32, device="cuda")
+    B.gemm(dA, dB, dP, M=M, N=N, K=K, transA=0, lda=K, transB=1, ldb=K, ldc=N, fp32=2)
+    off = torch.tensor(_cmap_offsets(M, N, R, 0, 0, R, M * R), device="cuda")
+    assert torch.equal(dM[off], dP)
+    with pytest.raises(B.PPError):
+        B.gemm(dA, dB, dP, M=M, N=N, K=K, transA=1, lda=M, transB=1, ldb=K, ldc=N, fp32=2)
+
+
 @pytest.mark.parametrize("fp32", [False, True])
 def test_gemm_long_rows(B, fp32):
     """A k-contiguous left operand with few rows and a row stride of 2^28 + 64 elements

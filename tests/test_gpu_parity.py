@@ -207,17 +207,40 @@ def test_fp32_products_within_single_precision(P):
         assert err <= 2e-6 * np.abs(corr).max() + 1e-14, (j, err, np.abs(corr).max())
 
 
+def test_split_bf16_products(P):
+    """Split-BF16 amplitude contraction (FP32 elsewhere, FP64 diagonal and assembly): the
+    products agree with the oracle to the split's accuracy, a relative 2^-16 per product,
+    on the parts beyond the diagonal."""
+    torch = pytest.importorskip("torch")
+    sys = _sys("mid")
+    X = random_block(5, sys.N, 2)
+    V = torch.tensor(np.concatenate([X[:, 0], X[:, 1]]), dtype=torch.float64, device="cuda")
+    outs = [torch.empty_like(V) for _ in range(3)]
+    A, B, S = dense.assemble(sys, 2)
+    A1, B1, _ = dense.assemble(sys, 1)
+    with P.Handle.from_system(sys, order=2, precision=P.PP_SPLIT_BF16) as h:
+        h.products(V, outs[0], outs[1], outs[2], fp32=True)
+    Vh = V.cpu().numpy()
+    ref = [(A @ Vh.T).T, (B @ Vh.T).T, (S @ Vh.T).T]
+    second = [((A - A1) @ Vh.T).T, ((B - B1) @ Vh.T).T, ref[2] - Vh]
+    for j in range(3):
+        err = np.abs(outs[j].cpu().numpy() - ref[j]).max()
+        assert err <= 1e-4 * np.abs(second[j]).max() + 1e-12, (j, err, np.abs(second[j]).max())
+
+
+@pytest.mark.parametrize("prec", ["fp32", "sbf16"])
 @pytest.mark.parametrize("omega0,nr", [(0.45, 8), (1.1, 8)])
-def test_window_mixed_precision(P, omega0, nr):
-    """FP32 subspace products with FP64 restarts and FP64 residual acceptance meet the FP64 bar."""
+def test_window_mixed_precision(P, omega0, nr, prec):
+    """FP32 (or split-BF16 amplitude) subspace products with FP64 restarts and FP64 residual
+    acceptance meet the FP64 bar."""
     sys = gen(7, 12, 40, 100)
-    with P.Handle.from_system(sys, order=2, precision=P.PP_FP32) as h:
+    with P.Handle.from_system(sys, order=2, precision=P.PP_FP32 if prec == "fp32" else P.PP_SPLIT_BF16) as h:
         e, vec, f, info = h.window_solve(omega0, nr)
     _check_window(sys, 2, omega0, nr, e, vec, f, info)
     assert np.all(info["residual"] <= 1e-9)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "sbf16"])
 def test_window_survey_completeness(P, precision):
     """The full 40/160/600 workload in the launch configuration the benchmark times
     (amplitudes stored, windows batched): 24 windows across the spectrum, each must
@@ -229,7 +252,7 @@ def test_window_survey_completeness(P, precision):
     survey = g["survey"] if precision == "fp64" else g["survey"][::3]
     from synth.gen import gen_config
     sys = gen_config("mp2_o40_v160_x600")
-    prec = P.PP_FP64 if precision == "fp64" else P.PP_FP32
+    prec = {"fp64": P.PP_FP64, "fp32": P.PP_FP32, "sbf16": P.PP_SPLIT_BF16}[precision]
     print(f"[survey] {len(survey)} windows, {precision}", flush=True)
     with P.Handle.from_system(sys, order=2, store_amplitudes=1, precision=prec) as h:
         for b0 in range(0, len(survey), 8):

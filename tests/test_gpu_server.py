@@ -118,10 +118,12 @@ def test_server_rejects_and_delivers_once(P):
             srv.poll(rid)
 
 
-def test_server_mixed_precision(P):
-    """FP32 contractions with FP64 refinement inside the server meet the FP64 bar."""
+@pytest.mark.parametrize("prec", ["fp32", "sbf16"])
+def test_server_mixed_precision(P, prec):
+    """FP32 contractions (the amplitude one as split-BF16 products in sbf16 mode) with FP64
+    refinement inside the server meet the FP64 bar."""
     systems = _systems()[:4]
-    with P.Server(precision=P.PP_FP32) as srv:
+    with P.Server(precision=P.PP_FP32 if prec == "fp32" else P.PP_SPLIT_BF16) as srv:
         ids = [srv.submit_system(s, w, nr) for s, w, nr in systems]
         res = [srv.wait(i) for i in ids]
     for (s, w, nr), r in zip(systems, res):
