@@ -59,6 +59,7 @@ struct NotSupported : std::runtime_error {
 // column n at (n / cRn) * cSn + n % cRn (0 leaves them plain), so a product whose
 // output is a strided block of a larger array is written in place.  With a column
 // split, column n is mapped as column cBn + n (a launch covering part of the columns).
+// The strides cSm, cSn and the base cBn are non-negative.
 //
 // splitk > 0 fixes the number of reduction splits (1: none; the workspace must hold
 // splitk * M * N * batches elements); 0 lets the launch choose.  tile = 64 selects the
