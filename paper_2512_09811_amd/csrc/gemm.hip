@@ -331,7 +331,10 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmDesc& d, double alpha, c
 // so that profiles can attribute its time); the code is identical.
 // One workgroup's tile of C (or, with W, of split 'split' of its reduction) for the
 // flattened (batch, tile) index 'flat' of GEMM d.
-template <typename T, int BM, int BN, int BK, bool AK, bool BKC>
+// CPF (C prefetch): the C elements an accumulating tile (beta != 0, no split-K, plain
+// C) will update are loaded before the reduction instead of after it, so their latency
+// hides behind a short reduction; the arithmetic of the update is unchanged.
+template <typename T, int BM, int BN, int BK, bool AK, bool BKC, bool CPF = false>
 __device__ __forceinline__ void gemm_tile(const GemmDesc& d, T alpha, const T* __restrict__ A,
                                           const T* __restrict__ B, T beta, T* __restrict__ C, T* __restrict__ W,
                                           int splitk, long flat, int split) {
@@ -397,6 +400,19 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& d, T alpha, const T* _
     else { n = 2 * (p % (BN / 2)); k = p / (BN / 2); }
   };
   pair_t ra[PA], rb[PB];
+  T cpre[CPF ? TM : 1][CPF ? TN : 1][4];
+  if constexpr (CPF) {
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = m0 + wm * WTM + i * 16 + Mfma<T>::row(lane, r);
+          const int col = n0 + wn * WTN + j * 16 + (lane & 15);
+          cpre[i][j][r] = (row < d.M && col < d.N) ? C[b1 * d.sC1 + b2 * d.sC2 + (long)row * d.ldc + col] : T(0);
+        }
+  }
   // Tile base pointers are advanced per iteration (wave-uniform 64-bit); per-element
   // offsets inside a tile are 32-bit (row * ld + k stays below 2^31 for every shape
   // the library issues), which keeps register pressure low enough for 2 waves/SIMD.
@@ -550,19 +566,24 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& d, T alpha, const T* _
           } else {
             T* cp = C + b1 * d.sC1 + b2 * d.sC2 + (long)row * d.ldc + col;
             T out = alpha * v;
-            if (beta != T(0)) out += beta * (*cp);
+            if constexpr (CPF) {
+              out += beta * cpre[i][j][r];
+            } else {
+              if (beta != T(0)) out += beta * (*cp);
+            }
             *cp = out;
           }
         }
       }
 }
 
+// TAG 4: the C-prefetch variant of the register-staged tile (see gemm_tile).
 template <typename T, int BM, int BN, int BK, bool AK, bool BKC, int TAG>
 __global__ __launch_bounds__(kThreads, 2) void gemm_kernel(GemmDesc d, T alpha, const T* __restrict__ A,
                                                         const T* __restrict__ B, T beta, T* __restrict__ C,
                                                         T* __restrict__ W, int splitk) {
-  gemm_tile<T, BM, BN, BK, AK, BKC>(d, alpha, A, B, beta, C, W, splitk, xcd_remap(blockIdx.x, (long)gridDim.x),
-                                    blockIdx.y);
+  gemm_tile<T, BM, BN, BK, AK, BKC, TAG == 4>(d, alpha, A, B, beta, C, W, splitk,
+                                              xcd_remap(blockIdx.x, (long)gridDim.x), blockIdx.y);
 }
 
 // Up to kGroupMax independent GEMMs of one tile shape in one grid: member g owns the
@@ -692,6 +713,14 @@ void launch(const GemmDesc& d, T alpha, const T* A, const T* B, T beta, T* C, hi
       throw InvalidArg("gemm: workspace too small for the requested reduction splits");
   }
   dim3 grid((unsigned)(ntiles * nbatch), (unsigned)splitk, 1);
+  if constexpr (TAG == 0 && BM == 64 && !(std::is_same<T, double>::value && AK && BKC)) {
+    // short accumulating reductions: load C before the reduction (same arithmetic)
+    if (splitk == 1 && beta != T(0) && total <= 4 && !(d.cRm | d.cRn)) {
+      gemm_kernel<T, BM, BN, BK, AK, BKC, 4><<<grid, kThreads, 0, s>>>(d, alpha, A, B, beta, C, nullptr, 1);
+      PPW_LAUNCH_CHECK();
+      return;
+    }
+  }
   if (splitk == 1) {
     gemm_kernel<T, BM, BN, BK, AK, BKC, TAG><<<grid, kThreads, 0, s>>>(d, alpha, A, B, beta, C, nullptr, 1);
     PPW_LAUNCH_CHECK();
