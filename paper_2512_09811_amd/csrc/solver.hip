@@ -592,11 +592,36 @@ class Solver {
 
   template <typename T>
   T* get(size_t n, const char* w) {
+    const size_t bytes = ((n * sizeof(T) + 255) / 256) * 256;  // the arena's block rounding
+    if (sizing_) {
+      slab_need_ += bytes;
+      return nullptr;
+    }
+    if (slab_ && slab_off_ + bytes <= slab_need_) {
+      T* p = reinterpret_cast<T*>(slab_ + slab_off_);
+      slab_off_ += bytes;
+      return p;
+    }
     T* p = c_.arena.alloc<T>(n, w);
     owned_.push_back(p);
     return p;
   }
+  // The solver's buffers are carved from one arena block: a sizing pass adds up their
+  // rounded sizes, then a single allocation (one hipMalloc instead of about seventy) is
+  // cut in the same order.
+  size_t slab_need_ = 0, slab_off_ = 0;
+  char* slab_ = nullptr;
+  bool sizing_ = false;
   void alloc() {
+    sizing_ = true;
+    carve();
+    sizing_ = false;
+    slab_ = c_.arena.alloc<char>(slab_need_, "window solver buffers");
+    owned_.push_back(slab_);
+    carve();
+    PPW_HIP(hipMemsetAsync(Q_, 0, sizeof(double) * (size_t)nbmax_ * N_, s_));
+  }
+  void carve() {
     const size_t bN = (size_t)nbmax_ * N_;
     const size_t kN = (size_t)kmax_ * N_;
     Q_ = get<double>(bN, "basis Q");
@@ -666,7 +691,6 @@ class Solver {
     noise_ = get<double>((size_t)2 * m_ * N_, "noise");
     wsp_.bytes = (size_t)32 << 20;
     wsp_.ptr = get<char>(wsp_.bytes, "solver split-K workspace");
-    PPW_HIP(hipMemsetAsync(Q_, 0, sizeof(double) * bN, s_));
   }
 
   void gemm(const GemmDesc& d, double a, const double* A, const double* B, double b, double* C) {
