@@ -22,8 +22,11 @@ extern "C" {
  * -> B[k*ldb+n], 1 -> B[n*ldb+k]; batch b offsets b*sA, b*sB, b*sC; outer reduction
  * kb offsets kb*sAk, kb*sBk).  fp32 = 1 runs the FP32 matrix-core kernel on float
  * arrays, fp32 = 2 the split-BF16 kernel on float arrays (transA = 0, transB = 1, no
- * batch or outer reduction, else PP_EINVAL).  ws_bytes of scratch are allocated for
- * split-K (0 = no split). */
+ * batch or outer reduction, else PP_EINVAL; the operands are copied into zero-padded
+ * rows of a multiple of 8 values and split there, as the library does with its own),
+ * fp32 = 3 the split-BF16 kernel on operands already in the split layout of
+ * ppint_split_sbf16 (lda, ldb multiples of 8 and >= K, 16-byte aligned, else PP_EINVAL).
+ * ws_bytes of scratch are allocated for split-K (0 = no split). */
 pp_status ppint_gemm(int32_t fp32, int32_t M, int32_t N, int32_t K, int32_t KB, int32_t nbatch, int32_t transA,
                      int64_t lda, int64_t sA, int64_t sAk, int32_t transB, int64_t ldb, int64_t sB, int64_t sBk,
                      int64_t ldc, int64_t sC, double alpha, const void* A, const void* B, double beta, void* C,
@@ -36,6 +39,12 @@ pp_status ppint_gemm(int32_t fp32, int32_t M, int32_t N, int32_t K, int32_t KB, 
 pp_status ppint_gemm_cmap(int32_t fp32, int32_t M, int32_t N, int32_t K, int32_t transA, int64_t lda, int32_t transB,
                           int64_t ldb, int64_t ldc, int32_t cRm, int64_t cSm, int32_t cRn, int64_t cSn, double alpha,
                           const void* A, const void* B, double beta, void* C, uint64_t ws_bytes);
+
+/* The split layout of the split-BF16 products, in place on n float values (device, n a
+ * multiple of 8, 16-byte aligned): every chunk of 8 values becomes 8 bf16 hi parts
+ * hi = bf16(x) (round to nearest even) followed by 8 bf16 lo parts lo = bf16(x - hi).
+ * PP_EINVAL for other n or alignment. */
+pp_status ppint_split_sbf16(int64_t n, float* x);
 
 /* One member of ppint_gemm_group (layouts as in ppint_gemm, no batch). */
 typedef struct {

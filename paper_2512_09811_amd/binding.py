@@ -131,6 +131,8 @@ def lib() -> C.CDLL:
         L.ppint_gemm_cmap.argtypes = [i32, i32, i32, i32, i32, i64, i32, i64, i64, i32, i64, i32, i64, dbl, vp, vp,
                                       dbl, vp, C.c_uint64]
         L.ppint_gemm_cmap.restype = C.c_int
+        L.ppint_split_sbf16.argtypes = [i64, vp]
+        L.ppint_split_sbf16.restype = C.c_int
         L.ppint_gemm_group.argtypes = [i32, i32, C.POINTER(ppint_gemm_member), C.POINTER(i32)]
         L.ppint_gemm_group.restype = C.c_int
         L.ppint_partial_syev.argtypes = [i32, vp, dbl, i32, vp, vp, C.POINTER(i32)]
@@ -362,6 +364,11 @@ def gemm_cmap(A, B, C_, *, M, N, K, transA=0, lda, transB=0, ldb, ldc, cRm=0, cS
     st = lib().ppint_gemm_cmap(int(fp32), M, N, K, transA, lda, transB, ldb, ldc, cRm, cSm, cRn, cSn, alpha,
                                A.data_ptr(), B.data_ptr(), beta, C_.data_ptr(), ws_bytes)
     _check(st)
+
+
+def split_sbf16(x):
+    """In-place split of a float32 device tensor into the split-BF16 chunk layout (test hook)."""
+    _check(lib().ppint_split_sbf16(x.numel(), x.data_ptr()))
 
 
 def gemm_group(members, fp32=False) -> int:

@@ -347,6 +347,51 @@ const char* pp_last_error(const pp_handle* h) {
 // ---------------------------------------------------------------------------
 // test hooks
 // ---------------------------------------------------------------------------
+namespace {
+// The split-BF16 GEMM on FP32 operands in the plain layout (A [M][lda], B [N][ldb], both
+// contiguous along k): the operands are copied into zero-padded rows of a multiple of 8
+// values, split there and multiplied.
+void sbf16_from_f32(ppw::GemmDesc d, float alpha, const float* A, const float* B, float beta, float* C) {
+  if (d.transA != 0 || d.transB == 0 || d.KB != 1 || d.nb1 != 1 || d.nb2 != 1)
+    throw ppw::InvalidArg("split-BF16 GEMM: operands contiguous along k, no batch or outer reduction");
+  if (d.M <= 0 || d.N <= 0) return;
+  if (d.K <= 0) throw ppw::InvalidArg("gemm: empty reduction");
+  const long ld = ((long)(d.K + 7) / 8) * 8;
+  float* As = nullptr;
+  float* Bs = nullptr;
+  try {
+    PPW_HIP(hipMalloc(&As, sizeof(float) * d.M * ld));
+    PPW_HIP(hipMalloc(&Bs, sizeof(float) * d.N * ld));
+    PPW_HIP(hipMemset(As, 0, sizeof(float) * d.M * ld));
+    PPW_HIP(hipMemset(Bs, 0, sizeof(float) * d.N * ld));
+    PPW_HIP(hipMemcpy2D(As, sizeof(float) * ld, A, sizeof(float) * d.lda, sizeof(float) * d.K, d.M,
+                        hipMemcpyDeviceToDevice));
+    PPW_HIP(hipMemcpy2D(Bs, sizeof(float) * ld, B, sizeof(float) * d.ldb, sizeof(float) * d.K, d.N,
+                        hipMemcpyDeviceToDevice));
+    ppw::split_sbf16((long)d.M * ld, As, nullptr);
+    ppw::split_sbf16((long)d.N * ld, Bs, nullptr);
+    d.lda = ld;
+    d.ldb = ld;
+    ppw::gemm_sbf16(d, alpha, As, Bs, beta, C, nullptr);
+    PPW_HIP(hipDeviceSynchronize());
+  } catch (...) {
+    (void)hipFree(As);
+    (void)hipFree(Bs);
+    throw;
+  }
+  (void)hipFree(As);
+  (void)hipFree(Bs);
+}
+}  // namespace
+
+pp_status ppint_split_sbf16(int64_t n, float* x) {
+  g_setup_error.clear();
+  return guarded(&g_setup_error, [&] {
+    ppw::split_sbf16(n, x, nullptr);
+    PPW_HIP(hipDeviceSynchronize());
+  });
+}
+
 pp_status ppint_gemm(int32_t fp32, int32_t M, int32_t N, int32_t K, int32_t KB, int32_t nbatch, int32_t transA,
                      int64_t lda, int64_t sA, int64_t sAk, int32_t transB, int64_t ldb, int64_t sB, int64_t sBk,
                      int64_t ldc, int64_t sC, double alpha, const void* A, const void* B, double beta, void* C,
@@ -376,8 +421,10 @@ pp_status ppint_gemm(int32_t fp32, int32_t M, int32_t N, int32_t K, int32_t KB, 
       w.ptr = ws;
       w.bytes = ws_bytes;
     }
-    if (fp32 == 2)
-      ppw::gemm_f32_sbf16(d, (float)alpha, (const float*)A, (const float*)B, (float)beta, (float*)C, nullptr);
+    if (fp32 == 3)
+      ppw::gemm_sbf16(d, (float)alpha, (const float*)A, (const float*)B, (float)beta, (float*)C, nullptr);
+    else if (fp32 == 2)
+      sbf16_from_f32(d, (float)alpha, (const float*)A, (const float*)B, (float)beta, (float*)C);
     else if (fp32)
       ppw::gemm_f32(d, (float)alpha, (const float*)A, (const float*)B, (float)beta, (float*)C, nullptr, w);
     else
@@ -413,8 +460,10 @@ pp_status ppint_gemm_cmap(int32_t fp32, int32_t M, int32_t N, int32_t K, int32_t
       w.ptr = ws;
       w.bytes = ws_bytes;
     }
-    if (fp32 == 2)
-      ppw::gemm_f32_sbf16(d, (float)alpha, (const float*)A, (const float*)B, (float)beta, (float*)C, nullptr);
+    if (fp32 == 3)
+      ppw::gemm_sbf16(d, (float)alpha, (const float*)A, (const float*)B, (float)beta, (float*)C, nullptr);
+    else if (fp32 == 2)
+      sbf16_from_f32(d, (float)alpha, (const float*)A, (const float*)B, (float)beta, (float*)C);
     else if (fp32)
       ppw::gemm_f32(d, (float)alpha, (const float*)A, (const float*)B, (float)beta, (float*)C, nullptr, w);
     else

@@ -93,10 +93,16 @@ void gemm_f32(const GemmDesc& d, float alpha, const float* A, const float* B, fl
 void gemm_f64_hhat(const GemmDesc& d, double alpha, const double* A, const double* B, double beta, double* C,
                    hipStream_t s, Workspace ws = {});
 // Split-BF16 product (three BF16 MFMAs per FP32 product, FP32 accumulation, relative
-// error about 2^-16): operands contiguous along k, no batch or outer reduction; C
-// index splits allowed.  Used for the amplitude contraction in PP_SPLIT_BF16 mode.
-void gemm_f32_sbf16(const GemmDesc& d, float alpha, const float* A, const float* B, float beta, float* C,
-                    hipStream_t s);
+// error about 2^-16) on operands held in the split layout of split_sbf16: operands
+// contiguous along k with leading dimensions a multiple of 8 values (and >= K), 16-byte
+// aligned, zero past K in a row's last chunk; no batch or outer reduction; C index splits
+// allowed.  Used for the amplitude contraction (and the amplitude strips' integrals) in
+// PP_SPLIT_BF16 mode.
+void gemm_sbf16(const GemmDesc& d, float alpha, const float* A, const float* B, float beta, float* C, hipStream_t s);
+// Splits n FP32 values in place (n a multiple of 8, x 16-byte aligned): each chunk of 8
+// values becomes their 8 bf16 hi parts, hi = bf16(x) rounded to nearest even, followed
+// by their 8 lo parts, lo = bf16(x - hi).
+void split_sbf16(long n, float* x, hipStream_t s);
 void gemm_f32_hhat(const GemmDesc& d, float alpha, const float* A, const float* B, float beta, float* C,
                    hipStream_t s, Workspace ws = {});
 

@@ -152,6 +152,8 @@ class EventLog {
 struct Context {
   int o = 0, v = 0, naux = 0, order = 0;
   long N = 0;
+  long N8 = 0;  // N rounded up to a multiple of 8: row stride of the FP32 G and amplitude strips
+  int X8 = 0;   // naux rounded up to a multiple of 8
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -183,6 +185,9 @@ struct Context {
   float *Bov32 = nullptr, *Boo32 = nullptr, *Bvv32 = nullptr, *BovLam32 = nullptr, *Boo_t32 = nullptr,
         *R32 = nullptr, *tau32 = nullptr;
   float *Gv32 = nullptr, *Ev32 = nullptr, *Go32 = nullptr, *Eo32 = nullptr;
+  // split-BF16 operands (split layout of split_sbf16): stored amplitudes [N][N8] and,
+  // for amplitudes rebuilt in strips, B^ov transposed [N][X8]
+  float *tau_sbf = nullptr, *BovT_sbf = nullptr;
 
   // product workspace (grown on demand)
   int kcap = 0;
@@ -246,12 +251,14 @@ struct Footprint {
   size_t setup_peak, steady;
 };
 Footprint context_footprint(int o, int v, int naux, int order, bool dip, bool store, int strip_rows, bool want_f32,
-                            int k);
+                            int k, bool split = false);
 
 // Grows the product workspace to k vectors ahead of time (no allocation in the loop).
 void sigma_reserve(Context& c, int k, int precision);
 
-// Algorithmic flops of one product pass over k vectors at the given order.
-double sigma_flops(const Context& c, int order, int k);
+// Algorithmic flops of one product pass over k vectors at the given order, with the
+// contractions of precision prec (0 FP64, 1 reduced); amplitudes that precision does not
+// store are rebuilt in strips, and their integrals count.
+double sigma_flops(const Context& c, int order, int k, int prec = 0);
 
 }  // namespace ppw

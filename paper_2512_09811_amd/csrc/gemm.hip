@@ -802,7 +802,7 @@ template <typename T>
 void single_dispatch(const GemmCall<T>& c, hipStream_t s) {
   if (c.tag == 2) {
     if constexpr (std::is_same<T, float>::value)
-      gemm_f32_sbf16(c.d, c.alpha, c.A, c.B, c.beta, c.C, s);
+      gemm_sbf16(c.d, c.alpha, c.A, c.B, c.beta, c.C, s);
     else
       throw InvalidArg("split-BF16 products take FP32 operands");
     return;
@@ -868,39 +868,41 @@ int gemm_group_impl(const std::vector<GemmCall<T>>& calls, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// FP32 product on BF16 matrix cores ("split BF16"): each FP32 operand x is split into
-// hi = bf16(x) (round to nearest even) and lo = bf16(x - hi), and a b is taken as
-// hi_a lo_b + lo_a hi_b + hi_a hi_b with FP32 accumulation; the dropped lo_a lo_b and the
-// rounding of lo leave a relative error of about 2^-16 per product.  Three 16x16x32 BF16
-// MFMAs per 16x16x32 block.  Operands contiguous along k (A [m][k], B [n][k]); 128 x 128
-// tiles of 2 x 2 wave64s; k tiles of 32 FP32 values staged in LDS (register prefetch)
-// with rows padded to 36 values, so the 16 rows of a fragment read fall on 16 different
-// groups of 4 banks.  Lane l reads row l % 16, k = 8 (l / 16) .. + 7 (the operand layout
-// of the 16x16x32 BF16 MFMA, checked on the device); results come in the FP32 MFMA layout.
+// Split-BF16 products.  An FP32 value x is carried as hi = bf16(x) (round to nearest
+// even) and lo = bf16(x - hi); a b is taken as hi_a lo_b + lo_a hi_b + hi_a hi_b with FP32
+// accumulation (the dropped lo_a lo_b and the rounding of lo leave about 2^-16 of |a b|
+// per product).  Operands are split once, in memory, before the product (split_sbf16):
+// a row of values is a sequence of 32-byte chunks, chunk c holding the bf16 hi parts of
+// values 8c .. 8c+7 and then their 8 lo parts.  A value still occupies 4 bytes, so rows
+// keep their FP32 strides (a multiple of 8 values) and an FP32 array is split in place.
+//
+// Kernel: 256 threads as 2 x 2 wave64s, BM x BN tiles; a k tile is 32 values = 4 chunks
+// = 128 B per row, loaded straight into LDS (global_load_lds_dwordx4) in the swizzled
+// slot layout of the FP64 kernel (16-byte slot s of row r at 8r + (s ^ ((r >> 1) & 7)),
+// logical slot 2c holding chunk c's hi parts and 2c + 1 its lo parts), so a fragment
+// read of 16 rows x 16 B touches every bank once and no conversion happens in the loop.
+// Three 16x16x32 BF16 MFMAs per 16 x 16 block and k tile; lane l supplies row l % 16,
+// chunk l / 16 (the operand layout of that MFMA, checked on the device); results come in
+// the FP32 MFMA layout.  Ragged tiles (an edge in m, n or k) are copied chunk by chunk
+// through registers into the same layout; values past K inside the last chunk of a row
+// must be zero (split_sbf16 of a zero-padded row leaves them so).
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
-constexpr int kSbBK = 32, kSbLD = 36;
+constexpr int kSbBK = 32;
 
-__device__ __forceinline__ void split8(const float* p, bf16x8_t& hi, bf16x8_t& lo) {
-  const f32x4_t x0 = *reinterpret_cast<const f32x4_t*>(p);
-  const f32x4_t x1 = *reinterpret_cast<const f32x4_t*>(p + 4);
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const __bf16 h0 = (__bf16)x0[t], h1 = (__bf16)x1[t];
-    hi[t] = h0;
-    hi[t + 4] = h1;
-    lo[t] = (__bf16)(x0[t] - (float)h0);
-    lo[t + 4] = (__bf16)(x1[t] - (float)h1);
-  }
-}
-
+template <int BM, int BN>
 __global__ __launch_bounds__(kThreads, 2) void gemm_sbf16_kernel(GemmDesc d, float alpha,
                                                                  const float* __restrict__ A,
                                                                  const float* __restrict__ B, float beta,
                                                                  float* __restrict__ C) {
-  constexpr int BM = 128, BN = 128, WTM = 64, WTN = 64, TM = 4, TN = 4, PL = BM * kSbBK / 4 / kThreads;
-  __shared__ __attribute__((aligned(16))) float As[2][BM * kSbLD];
-  __shared__ __attribute__((aligned(16))) float Bs[2][BN * kSbLD];
+  constexpr int BK = kSbBK;
+  constexpr int WTM = BM / 2, WTN = BN / 2, TM = WTM / 16, TN = WTN / 16;
+  constexpr int SA = BM * BK, SB = BN * BK;  // storage floats per buffer
+  constexpr int CA = BM / 32, CB = BN / 32;  // 1 KB wave loads per operand tile (8 rows each)
+  __shared__ __attribute__((aligned(16))) float As0[SA];
+  __shared__ __attribute__((aligned(16))) float As1[SA];
+  __shared__ __attribute__((aligned(16))) float Bs0[SB];
+  __shared__ __attribute__((aligned(16))) float Bs1[SB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
   const int tiles_m = (d.M + BM - 1) / BM, tiles_n = (d.N + BN - 1) / BN;
   int tm, tn;
@@ -910,38 +912,48 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_sbf16_kernel(GemmDesc d, flo
   const float* Bt = B + (long)n0 * d.ldb;
   const int lda32 = (int)d.lda, ldb32 = (int)d.ldb;
   const int mrem = d.M - m0, nrem = d.N - n0;
-  const bool vec_ok = mrem >= BM && nrem >= BN && (d.lda % 4) == 0 && (d.ldb % 4) == 0 &&
-                      ((uintptr_t)At % 16) == 0 && ((uintptr_t)Bt % 16) == 0;
-  // slot q = i * 256 + tid of a k tile: row q / 8, four k values from 4 (q % 8)
-  f32x4_t ra[PL], rb[PL];
-  auto load = [&](int k0) {
-    const int krem = d.K - k0;
-    if (vec_ok && krem >= kSbBK) {
+  const bool rows_ok = mrem >= BM && nrem >= BN;
+  int offA[CA], offB[CB];
 #pragma unroll
-      for (int i = 0; i < PL; ++i) {
-        const int q = i * kThreads + tid, r = q >> 3, k4 = 4 * (q & 7);
-        ra[i] = *reinterpret_cast<const f32x4_t*>(At + r * lda32 + k0 + k4);
-        rb[i] = *reinterpret_cast<const f32x4_t*>(Bt + r * ldb32 + k0 + k4);
-      }
+  for (int c = 0; c < CA; ++c) {
+    const int sl = (wave + 4 * c) * 64 + lane, r = sl >> 3, sg = (sl & 7) ^ ((r >> 1) & 7);
+    offA[c] = r * lda32 + 4 * sg;
+  }
+#pragma unroll
+  for (int c = 0; c < CB; ++c) {
+    const int sl = (wave + 4 * c) * 64 + lane, r = sl >> 3, sg = (sl & 7) ^ ((r >> 1) & 7);
+    offB[c] = r * ldb32 + 4 * sg;
+  }
+  auto fill = [&](float* Ab, float* Bb, int kt) {
+    const int k0 = kt * BK;
+    const float* Ak = At + k0;
+    const float* Bk = Bt + k0;
+    if (rows_ok && d.K - k0 >= BK) {
+#pragma unroll
+      for (int c = 0; c < CA; ++c)
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(Ak + offA[c]),
+                                         (__attribute__((address_space(3))) void*)(Ab + (wave + 4 * c) * 256), 16, 0,
+                                         0);
+#pragma unroll
+      for (int c = 0; c < CB; ++c)
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(Bk + offB[c]),
+                                         (__attribute__((address_space(3))) void*)(Bb + (wave + 4 * c) * 256), 16, 0,
+                                         0);
     } else {
 #pragma unroll
-      for (int i = 0; i < PL; ++i) {
-        const int q = i * kThreads + tid, r = q >> 3, k4 = 4 * (q & 7);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int kk = k4 + t;
-          ra[i][t] = (r < mrem && kk < krem) ? At[r * lda32 + k0 + kk] : 0.0f;
-          rb[i][t] = (r < nrem && kk < krem) ? Bt[r * ldb32 + k0 + kk] : 0.0f;
-        }
+      for (int i = 0; i < SA / 4 / kThreads; ++i) {
+        const int q = i * kThreads + tid, r = q >> 3, sg = q & 7;
+        f32x4_t v = f32x4_t{0.f, 0.f, 0.f, 0.f};
+        if (r < mrem && k0 + 8 * (sg >> 1) < d.K) v = *reinterpret_cast<const f32x4_t*>(Ak + r * lda32 + 4 * sg);
+        *reinterpret_cast<f32x4_t*>(Ab + 4 * swz16(r, sg)) = v;
       }
-    }
-  };
-  auto store = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < PL; ++i) {
-      const int q = i * kThreads + tid, r = q >> 3, k4 = 4 * (q & 7);
-      *reinterpret_cast<f32x4_t*>(&As[buf][r * kSbLD + k4]) = ra[i];
-      *reinterpret_cast<f32x4_t*>(&Bs[buf][r * kSbLD + k4]) = rb[i];
+      for (int i = 0; i < SB / 4 / kThreads; ++i) {
+        const int q = i * kThreads + tid, r = q >> 3, sg = q & 7;
+        f32x4_t v = f32x4_t{0.f, 0.f, 0.f, 0.f};
+        if (r < nrem && k0 + 8 * (sg >> 1) < d.K) v = *reinterpret_cast<const f32x4_t*>(Bk + r * ldb32 + 4 * sg);
+        *reinterpret_cast<f32x4_t*>(Bb + 4 * swz16(r, sg)) = v;
+      }
     }
   };
   f32x4_t acc[TM][TN];
@@ -949,20 +961,22 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_sbf16_kernel(GemmDesc d, flo
   for (int i = 0; i < TM; ++i)
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-  const int nkt = (d.K + kSbBK - 1) / kSbBK;
-  load(0);
-  store(0);
-  __syncthreads();
-  const int kq = 8 * (lane >> 4);
-  int buf = 0;
-  for (int kt = 0; kt < nkt; ++kt) {
-    const bool more = kt + 1 < nkt;
-    if (more) load((kt + 1) * kSbBK);
+  const int ch = lane >> 4, rl = lane & 15;
+  // one k tile: B fragments first, then A row blocks in the order the MFMAs use them
+  auto tile = [&](const float* Ab, const float* Bb) {
     bf16x8_t ah[TM], al[TM], bh[TN], bl[TN];
 #pragma unroll
-    for (int i = 0; i < TM; ++i) split8(&As[buf][(wm * WTM + i * 16 + (lane & 15)) * kSbLD + kq], ah[i], al[i]);
+    for (int j = 0; j < TN; ++j) {
+      const int r = wn * WTN + j * 16 + rl;
+      bh[j] = *reinterpret_cast<const bf16x8_t*>(Bb + 4 * swz16(r, 2 * ch));
+      bl[j] = *reinterpret_cast<const bf16x8_t*>(Bb + 4 * swz16(r, 2 * ch + 1));
+    }
 #pragma unroll
-    for (int j = 0; j < TN; ++j) split8(&Bs[buf][(wn * WTN + j * 16 + (lane & 15)) * kSbLD + kq], bh[j], bl[j]);
+    for (int i = 0; i < TM; ++i) {
+      const int r = wm * WTM + i * 16 + rl;
+      ah[i] = *reinterpret_cast<const bf16x8_t*>(Ab + 4 * swz16(r, 2 * ch));
+      al[i] = *reinterpret_cast<const bf16x8_t*>(Ab + 4 * swz16(r, 2 * ch + 1));
+    }
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -971,9 +985,21 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_sbf16_kernel(GemmDesc d, flo
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
       }
-    if (more) store(buf ^ 1);
+  };
+  const int nkt = (d.K + BK - 1) / BK;
+  fill(As0, Bs0, 0);
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's loads into LDS have landed
+  __syncthreads();
+  auto step = [&](const float* Ac, const float* Bc, float* An, float* Bn, int kt) {
+    const bool more = kt + 1 < nkt;
+    if (more) fill(An, Bn, kt + 1);
+    tile(Ac, Bc);
+    if (more) __builtin_amdgcn_s_waitcnt(0x0F70);
     __syncthreads();
-    buf ^= 1;
+  };
+  for (int kt = 0; kt < nkt; kt += 2) {
+    step(As0, Bs0, As1, Bs1, kt);
+    if (kt + 1 < nkt) step(As1, Bs1, As0, Bs0, kt + 1);
   }
   if (d.cRm | d.cRn) {
     store_mapped<float, f32x4_t, TM, TN, WTM, WTN>(d, alpha, beta, C, m0, n0, wm, wn, lane, acc);
@@ -996,6 +1022,24 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_sbf16_kernel(GemmDesc d, flo
       }
 }
 
+// In-place split of n / 8 chunks of 8 FP32 values into the chunk layout above.
+__global__ void split_sbf16_kernel(long nchunks, float* __restrict__ x) {
+  for (long c = blockIdx.x * (long)blockDim.x + threadIdx.x; c < nchunks; c += (long)gridDim.x * blockDim.x) {
+    f32x4_t* p = reinterpret_cast<f32x4_t*>(x + 8 * c);
+    const f32x4_t a = p[0], b = p[1];
+    bf16x8_t hi, lo;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      hi[t] = (__bf16)a[t];
+      hi[t + 4] = (__bf16)b[t];
+      lo[t] = (__bf16)(a[t] - (float)hi[t]);
+      lo[t + 4] = (__bf16)(b[t] - (float)hi[t + 4]);
+    }
+    *reinterpret_cast<bf16x8_t*>(x + 8 * c) = hi;
+    *reinterpret_cast<bf16x8_t*>(x + 8 * c + 4) = lo;
+  }
+}
+
 }  // namespace
 
 int gemm_auto_splitk(const GemmDesc& d, size_t ws_bytes, bool fp32) {
@@ -1009,14 +1053,30 @@ int gemm_auto_splitk(const GemmDesc& d, size_t ws_bytes, bool fp32) {
   return auto_splitk(ntiles * nbatch, total, per, ws_bytes);
 }
 
-void gemm_f32_sbf16(const GemmDesc& d, float alpha, const float* A, const float* B, float beta, float* C,
-                    hipStream_t s) {
+void gemm_sbf16(const GemmDesc& d, float alpha, const float* A, const float* B, float beta, float* C, hipStream_t s) {
   if (d.M <= 0 || d.N <= 0) return;
   if (d.K <= 0) throw InvalidArg("gemm: empty reduction");
   if (d.transA != 0 || d.transB == 0 || d.KB != 1 || d.nb1 != 1 || d.nb2 != 1)
     throw InvalidArg("split-BF16 GEMM: operands contiguous along k, no batch or outer reduction");
-  const long wgs = checked_workgroups<128, 128, kSbBK>(d);
-  gemm_sbf16_kernel<<<dim3((unsigned)wgs), kThreads, 0, s>>>(d, alpha, A, B, beta, C);
+  if (d.lda % 8 || d.ldb % 8 || d.lda < d.K || d.ldb < d.K || (uintptr_t)A % 16 || (uintptr_t)B % 16)
+    throw InvalidArg("split-BF16 GEMM: operand rows must start on 32-byte chunks (leading dimensions a multiple "
+                     "of 8 values and at least K, 16-byte aligned operands)");
+  if (d.M >= 96 && d.N >= 96) {
+    const long wgs = checked_workgroups<128, 128, kSbBK>(d);
+    gemm_sbf16_kernel<128, 128><<<dim3((unsigned)wgs), kThreads, 0, s>>>(d, alpha, A, B, beta, C);
+  } else {
+    const long wgs = checked_workgroups<64, 64, kSbBK>(d);
+    gemm_sbf16_kernel<64, 64><<<dim3((unsigned)wgs), kThreads, 0, s>>>(d, alpha, A, B, beta, C);
+  }
+  PPW_LAUNCH_CHECK();
+}
+
+void split_sbf16(long n, float* x, hipStream_t s) {
+  if (n <= 0) return;
+  if (n % 8 || (uintptr_t)x % 16) throw InvalidArg("split_sbf16: a whole number of 8-value chunks, 16-byte aligned");
+  const long chunks = n / 8;
+  const int blocks = (int)std::max<long>(1, std::min<long>((chunks + 255) / 256, 65536));
+  split_sbf16_kernel<<<blocks, 256, 0, s>>>(chunks, x);
   PPW_LAUNCH_CHECK();
 }
 

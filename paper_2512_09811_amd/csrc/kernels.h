@@ -19,9 +19,10 @@ void permute3(const double* in, double* out, int d0, int d1, int d2, const int p
 void tau_strip(const double* S, int o, int v, int k0, int ib, const double* eps_o, const double* eps_v,
                double* tau, double* t, double* tEv, double* tEo, double* partial, hipStream_t s);
 long tau_blocks(int o, int v, int ib);
-// Same strip built in FP32 (for the reduced-precision product path): tau only.
+// Same strip built in FP32 (for the reduced-precision product path): tau only, rows of
+// ld >= o v values (columns o v .. ld - 1 are not written).
 void tau_strip_f32(const float* S, int o, int v, int k0, int ib, const double* eps_o, const double* eps_v,
-                   float* tau, hipStream_t s);
+                   float* tau, long ld, hipStream_t s);
 
 // Deterministic sum of n doubles (single block).
 void sum_reduce(const double* x, long n, double* out, hipStream_t s);
@@ -51,6 +52,11 @@ void build_ring_operand(const double* Bov, const double* Lam, int o, int v, int 
 // y = alpha*x + beta*y (n elements), and conversions.
 void axpby(long n, double alpha, const double* x, double beta, double* y, hipStream_t s);
 void to_f32(long n, const double* x, float* y, hipStream_t s);
+// y[r][c] = x[r][c] (c < cols) and 0 (cols <= c < ldy) as FP32, for rows r < rows.
+void to_f32_rows(long rows, long cols, const double* x, long ldx, float* y, long ldy, hipStream_t s);
+// y[c][r] = x[r][c] (r < rows) and 0 (rows <= r < ldy) as FP32, for columns c < cols:
+// the transpose of a rows x cols FP64 array into zero-padded FP32 rows.
+void transpose_to_f32(long rows, long cols, const double* x, float* y, long ldy, hipStream_t s);
 // Excitonic density of states: out[2b] = #pairs with eps_a - eps_i in [edges[b], edges[b+1]),
 // out[2b+1] = their sum of squared dipoles (dip nullable).  Device pointers.
 void exciton_dos(int o, int v, const double* eo, const double* ev, const double* dip, const double* edges,

@@ -56,7 +56,7 @@ __global__ void permute3_kernel(const double* __restrict__ in, double* __restric
 
 template <typename T>
 __global__ void tau_strip_kernel(const T* __restrict__ S, int o, int v, int k0, int ib, const double* __restrict__ eo,
-                                 const double* __restrict__ ev, T* __restrict__ tau, double* __restrict__ t,
+                                 const double* __restrict__ ev, T* __restrict__ tau, long ldt, double* __restrict__ t,
                                  double* __restrict__ tEv, double* __restrict__ tEo, double* __restrict__ partial) {
   // block: one (k_local, l) pair and a 32x32 (x, y) tile; 256 threads, 4 elements each
   __shared__ T T1[32][33];
@@ -94,7 +94,7 @@ __global__ void tau_strip_kernel(const T* __restrict__ S, int o, int v, int k0, 
       const double tt = sxy / D;
       const double tu = (2.0 * sxy - syx) / D;
       const long idx = ((long)kloc * v + x) * N + (long)l * v + y;
-      if (tau) tau[idx] = (T)tu;
+      if (tau) tau[((long)kloc * v + x) * ldt + (long)l * v + y] = (T)tu;
       if (t) t[idx] = tt;
       if (tEv) tEv[idx] = tt * (ekl - ev[y]);
       if (tEo) tEo[idx] = tt * (eo[k] - ev[x] - ev[y]);
@@ -240,6 +240,32 @@ __global__ void dos_kernel(int o, int v, const double* __restrict__ eo, const do
   }
 }
 
+__global__ void to_f32_rows_kernel(long rows, long cols, const double* __restrict__ x, long ldx,
+                                   float* __restrict__ y, long ldy) {
+  const long n = rows * ldy;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < n; idx += (long)gridDim.x * blockDim.x) {
+    const long r = idx / ldy, c = idx % ldy;
+    y[idx] = c < cols ? (float)x[r * ldx + c] : 0.0f;
+  }
+}
+
+// 32 x 32 tiles through LDS: reads along x's rows, writes along y's rows.
+__global__ void transpose_to_f32_kernel(long rows, long cols, const double* __restrict__ x, float* __restrict__ y,
+                                        long ldy) {
+  __shared__ float tile[32][33];
+  const long r0 = (long)blockIdx.y * 32, c0 = (long)blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 256 threads: 8 rows of 32
+  for (int i = ty; i < 32; i += 8) {
+    const long r = r0 + i, c = c0 + tx;
+    tile[i][tx] = (r < rows && c < cols) ? (float)x[r * cols + c] : 0.0f;
+  }
+  __syncthreads();
+  for (int i = ty; i < 32; i += 8) {
+    const long c = c0 + i, r = r0 + tx;
+    if (c < cols && r < ldy) y[c * ldy + r] = tile[tx][i];
+  }
+}
+
 __global__ void to_f64_kernel(long n, const float* __restrict__ x, double* __restrict__ y) {
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
     y[i] = (double)x[i];
@@ -298,15 +324,16 @@ void tau_strip(const double* S, int o, int v, int k0, int ib, const double* eps_
                double* t, double* tEv, double* tEo, double* partial, hipStream_t s) {
   const int nt = (v + 31) / 32;
   dim3 grid(nt * nt, ib * o);
-  tau_strip_kernel<double><<<grid, 256, 0, s>>>(S, o, v, k0, ib, eps_o, eps_v, tau, t, tEv, tEo, partial);
+  tau_strip_kernel<double><<<grid, 256, 0, s>>>(S, o, v, k0, ib, eps_o, eps_v, tau, (long)o * v, t, tEv, tEo,
+                                                 partial);
   PPW_LAUNCH_CHECK();
 }
 
 void tau_strip_f32(const float* S, int o, int v, int k0, int ib, const double* eps_o, const double* eps_v, float* tau,
-                   hipStream_t s) {
+                   long ld, hipStream_t s) {
   const int nt = (v + 31) / 32;
   dim3 grid(nt * nt, ib * o);
-  tau_strip_kernel<float><<<grid, 256, 0, s>>>(S, o, v, k0, ib, eps_o, eps_v, tau, nullptr, nullptr, nullptr,
+  tau_strip_kernel<float><<<grid, 256, 0, s>>>(S, o, v, k0, ib, eps_o, eps_v, tau, ld, nullptr, nullptr, nullptr,
                                                 nullptr);
   PPW_LAUNCH_CHECK();
 }
@@ -352,6 +379,20 @@ void axpby(long n, double alpha, const double* x, double beta, double* y, hipStr
 
 void to_f32(long n, const double* x, float* y, hipStream_t s) {
   to_f32_kernel<<<grid_for(n), kBlock, 0, s>>>(n, x, y);
+  PPW_LAUNCH_CHECK();
+}
+
+void to_f32_rows(long rows, long cols, const double* x, long ldx, float* y, long ldy, hipStream_t s) {
+  to_f32_rows_kernel<<<grid_for(rows * ldy), kBlock, 0, s>>>(rows, cols, x, ldx, y, ldy);
+  PPW_LAUNCH_CHECK();
+}
+
+void transpose_to_f32(long rows, long cols, const double* x, float* y, long ldy, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return;
+  // padded rows of y (r >= rows up to ldy) are covered by the tiles of the last block row
+  const long brows = (std::max(rows, ldy) + 31) / 32, bcols = (cols + 31) / 32;
+  if (brows > 65535) throw InvalidArg("transpose_to_f32: too many rows");
+  transpose_to_f32_kernel<<<dim3((unsigned)bcols, (unsigned)brows), kBlock, 0, s>>>(rows, cols, x, y, ldy);
   PPW_LAUNCH_CHECK();
 }
 

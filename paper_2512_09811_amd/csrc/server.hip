@@ -117,7 +117,7 @@ class GroupBatcher : public ProductSink {
         j.BV = r->BV;
         j.SV = r->SV;
         jobs.push_back(j);
-        flops += sigma_flops(*r->ctx, r->ctx->order, r->k);
+        flops += sigma_flops(*r->ctx, r->ctx->order, r->k, r->prec);
       }
       hipEvent_t a, b;
       PPW_HIP(hipEventCreate(&a));
@@ -227,7 +227,8 @@ class Server {
       r.strip_rows = (int)std::max<double>(1.0, std::min<double>(r.o, cap / (5.0 * r.v * (double)N * 8.0)));
     }
     const int k = window_block_vectors((long)N, r.n_roots, so_);
-    const Footprint fp = context_footprint(r.o, r.v, r.naux, r.order, r.has_dip, r.store, r.strip_rows, f32, k);
+    const Footprint fp = context_footprint(r.o, r.v, r.naux, r.order, r.has_dip, r.store, r.strip_rows, f32, k,
+                                           opt_.precision == PP_SPLIT_BF16);
     r.bytes = std::max(fp.setup_peak, fp.steady + window_solve_bytes((long)N, r.n_roots, so_)) + ((size_t)1 << 20);
   }
 

@@ -73,7 +73,14 @@ int strip_rows_for(const Context& c, size_t bytes, int arrays) {
 
 }  // namespace
 
-double sigma_flops(const Context& c, int order, int k) {
+// Whether the amplitudes the given precision's products read are stored (else they are
+// rebuilt in strips in every pass).
+static bool amplitudes_stored(const Context& c, int prec) {
+  if (prec == 1) return c.split_bf16 ? c.tau_sbf != nullptr : c.tau32 != nullptr;
+  return c.tau != nullptr;
+}
+
+double sigma_flops(const Context& c, int order, int k, int prec) {
   if (order <= 0) return 0.0;
   const double o = c.o, v = c.v, X = c.naux, N = (double)c.N, K = k;
   double f = 0.0;
@@ -86,6 +93,7 @@ double sigma_flops(const Context& c, int order, int k) {
   if (order >= 2) {
     f += 2.0 * K * X * o * o * v;              // - B^oo_P V   (G)
     f += 2.0 * N * N * K * X;                  // H = tau G    (dominant)
+    if (!amplitudes_stored(c, prec)) f += 2.0 * N * N * X;  // (ia|jb) of the rebuilt strips
     f += 2.0 * K * X * o * v * v;              // H B^vv
     f += 2.0 * K * X * o * o * v;              // B^oo H
     f += 2.0 * K * o * v * v * 2.0;            // V Gv, V Ev
@@ -107,6 +115,8 @@ Context* setup_context(const SetupParams& p) {
     c->order = p.order;
     c->split_bf16 = p.split_bf16 && p.want_f32;
     c->N = (long)p.o * p.v;
+    c->N8 = (c->N + 7) / 8 * 8;
+    c->X8 = (p.naux + 7) / 8 * 8;
     c->device = p.device;
     PPW_HIP(hipSetDevice(p.device));
     if (p.stream) {
@@ -254,8 +264,21 @@ Context* setup_context(const SetupParams& p) {
       c->Bvv32 = cp32(c->Bvv, (size_t)X * v * v, "B_vv fp32");
       c->Boo_t32 = cp32(c->Boo_t, (size_t)o * o * X, "B_oo [i][j][P] fp32");
       c->R32 = cp32(c->R, (size_t)o * c->ns * X * v, "ring operand fp32");
+      if (p.order >= 2 && c->split_bf16) {
+        // operands of the split-BF16 amplitude products, split once here: the stored
+        // amplitudes, or B^ov transposed for the integrals of the rebuilt strips
+        if (c->tau) {
+          c->tau_sbf = c->arena.alloc<float>((size_t)N * c->N8, "amplitudes tau split-BF16");
+          to_f32_rows(N, N, c->tau, N, c->tau_sbf, c->N8, s);
+          split_sbf16(N * c->N8, c->tau_sbf, s);
+        } else {
+          c->BovT_sbf = c->arena.alloc<float>((size_t)N * c->X8, "B_ov transposed split-BF16");
+          transpose_to_f32(X, N, c->Bov, c->BovT_sbf, c->X8, s);
+          split_sbf16(N * c->X8, c->BovT_sbf, s);
+        }
+      }
       if (p.order >= 2) {
-        if (c->tau) c->tau32 = cp32(c->tau, (size_t)N * N, "amplitudes tau fp32");
+        if (c->tau && !c->split_bf16) c->tau32 = cp32(c->tau, (size_t)N * N, "amplitudes tau fp32");
         c->Gv32 = cp32(c->Gv, (size_t)v * v, "Gv fp32");
         c->Ev32 = cp32(c->Ev, (size_t)v * v, "Ev fp32");
         c->Go32 = cp32(c->Go, (size_t)o * o, "Go fp32");
@@ -320,14 +343,20 @@ void grow_workspace32(Context& c, int k) {
   regrow(c, c.w32_J, (size_t)k * N, "ws32 J");
   regrow(c, c.w32_P, (size_t)4 * k * N, "ws32 P");
   regrow(c, c.w32_c, (size_t)X * k, "ws32 c");
-  regrow(c, c.w32_G, (size_t)k * X * N, "ws32 G");
+  // G rows (q,P) of N8 values; the padding past N stays zero (split-BF16 chunks)
+  regrow(c, c.w32_G, (size_t)k * X * c.N8, "ws32 G");
+  PPW_HIP(hipMemsetAsync(c.w32_G, 0, sizeof(float) * k * X * c.N8, c.stream));
+  PPW_HIP(hipStreamSynchronize(c.stream));  // products may run on another stream
   regrow(c, c.w32_U, (size_t)k * o * c.ns * X * o, "ws32 U");
   if (c.order >= 2) {
-    const int ib = c.tau32 ? o : c.strip_rows;
+    const bool stored = amplitudes_stored(c, 1);
+    const int ib = stored ? o : c.strip_rows;
     regrow(c, c.w32_H, (size_t)ib * v * k * X, "ws32 H");
-    if (!c.tau32) {
+    if (!stored) {
       regrow(c, c.w32_S, (size_t)c.strip_rows * v * N, "ws32 strip S");
-      regrow(c, c.w32_tau, (size_t)c.strip_rows * v * N, "ws32 strip tau");
+      regrow(c, c.w32_tau, (size_t)c.strip_rows * v * c.N8, "ws32 strip tau");
+      PPW_HIP(hipMemsetAsync(c.w32_tau, 0, sizeof(float) * c.strip_rows * v * c.N8, c.stream));
+      PPW_HIP(hipStreamSynchronize(c.stream));
     }
   }
   c.kcap32 = k;
@@ -348,7 +377,7 @@ void gemm_t<float>(const GemmDesc& d, float a, const float* A, const float* B, f
 // Split-BF16 amplitude contraction (FP32 operands only).
 inline void gemm_sbf16_t(const GemmDesc& d, float a, const float* A, const float* B, float b, float* C,
                          hipStream_t s) {
-  gemm_f32_sbf16(d, a, A, B, b, C, s);
+  gemm_sbf16(d, a, A, B, b, C, s);
 }
 inline void gemm_sbf16_t(const GemmDesc&, double, const double*, const double*, double, double*, hipStream_t) {
   throw InvalidArg("split-BF16 products take FP32 operands");
@@ -367,28 +396,37 @@ void gemm_hhat_t<float>(const GemmDesc& d, float a, const float* A, const float*
   gemm_f32_hhat(d, a, A, B, b, C, s, ws);
 }
 inline void tau_strip_t(const double* S, int o, int v, int k0, int ib, const double* eo, const double* ev, double* tau,
-                        hipStream_t s) {
+                        long, hipStream_t s) {
   tau_strip(S, o, v, k0, ib, eo, ev, tau, nullptr, nullptr, nullptr, nullptr, s);
 }
 inline void tau_strip_t(const float* S, int o, int v, int k0, int ib, const double* eo, const double* ev, float* tau,
-                        hipStream_t s) {
-  tau_strip_f32(S, o, v, k0, ib, eo, ev, tau, s);
+                        long ld, hipStream_t s) {
+  tau_strip_f32(S, o, v, k0, ib, eo, ev, tau, ld, s);
 }
 
 // Operands and workspace of one precision.
+// ldG: row stride of G (rows (q,P)); ldtau: row stride of the stored amplitudes tau;
+// ldst: row stride of the amplitude strips tau_w.  With sbf, tau, tau_w and G are the
+// split-BF16 operands of the amplitude contraction (G split in place once built) and the
+// strips' integrals come from BovT (B^ov transposed, split, rows of X8 values).
 template <typename T>
 struct Ops {
   const T *Bov, *BovLam, *Boo, *Bvv, *Boo_t, *R, *tau, *Gv, *Ev, *Go, *Eo;
   T *c, *G, *U, *H, *S, *tau_w;
+  long ldG, ldtau, ldst;
+  bool sbf;
+  const T* BovT;
 };
 
 Ops<double> ops64(Context& c) {
   return Ops<double>{c.Bov, c.BovLam, c.Boo, c.Bvv, c.Boo_t, c.R, c.tau, c.Gv, c.Ev, c.Go, c.Eo,
-                     c.w_c, c.w_G, c.w_U, c.w_H, c.w_S, c.w_tau};
+                     c.w_c, c.w_G, c.w_U, c.w_H, c.w_S, c.w_tau, c.N, c.N, c.N, false, nullptr};
 }
 Ops<float> ops32(Context& c) {
-  return Ops<float>{c.BovLam32, c.BovLam32, c.Boo32, c.Bvv32, c.Boo_t32, c.R32, c.tau32, c.Gv32, c.Ev32, c.Go32,
-                    c.Eo32, c.w32_c, c.w32_G, c.w32_U, c.w32_H, c.w32_S, c.w32_tau};
+  const bool sbf = c.split_bf16 && c.order >= 2;
+  return Ops<float>{c.BovLam32, c.BovLam32, c.Boo32, c.Bvv32, c.Boo_t32, c.R32, sbf ? c.tau_sbf : c.tau32, c.Gv32,
+                    c.Ev32, c.Go32, c.Eo32, c.w32_c, c.w32_G, c.w32_U, c.w32_H, c.w32_S, c.w32_tau,
+                    c.N8, sbf ? c.N8 : c.N, c.N8, sbf, c.BovT_sbf};
 }
 
 // A product pass as a sequence of steps: launched as they are issued, or recorded
@@ -470,9 +508,9 @@ void contract(Context& c, const Ops<T>& t, Emit<T>& e, int order, int k, const T
   {
     GemmDesc d = gd(k * o, X * v, v, 0, v, 1, v, v);
     d.cRm = o;
-    d.cSm = (long)X * N;
+    d.cSm = (long)X * t.ldG;
     d.cRn = v;
-    d.cSn = N;
+    d.cSn = t.ldG;
     e.gemm(d, one, V, t.Bvv, zero, t.G, c.ws);
   }
   // AV = -K_A(V) = -sum_P Boo_P G1_P
@@ -480,9 +518,9 @@ void contract(Context& c, const Ops<T>& t, Emit<T>& e, int order, int k, const T
     GemmDesc d = gd(o, v, o, 0, o, 0, v, v);
     d.KB = X;
     d.sAk = (long)o * o;
-    d.sBk = N;
+    d.sBk = t.ldG;
     d.nb1 = k;
-    d.sB1 = (long)X * N;
+    d.sB1 = (long)X * t.ldG;
     d.sC1 = N;
     e.gemm(d, mone, t.Boo, t.G, zero, AV, c.ws);
   }
@@ -530,9 +568,15 @@ void contract(Context& c, const Ops<T>& t, Emit<T>& e, int order, int k, const T
     d.nb2 = X;
     d.sA2 = (long)o * o;
     d.sB1 = N;
-    d.sC1 = (long)X * N;
-    d.sC2 = N;
+    d.sC1 = (long)X * t.ldG;
+    d.sC2 = t.ldG;
     e.gemm(d, mone, t.Boo, V, one, t.G, c.ws);
+  }
+  if (t.sbf) {
+    // G is complete: split it in place for the split-BF16 amplitude products
+    T* G = t.G;
+    const long n = (long)k * X * t.ldG;
+    e.call([=](hipStream_t st) { split_sbf16(n, reinterpret_cast<float*>(G), st); });
   }
   const long kX = (long)k * X;
   // H = tau G is written as [q][(i,c)][P] for the ib occupied rows i of the strip (the
@@ -576,7 +620,7 @@ void contract(Context& c, const Ops<T>& t, Emit<T>& e, int order, int k, const T
   double hflops = 0.0;
   if (t.tau) {
     // H[q][(i,c)][P] = sum_(j,d) tau[(i,c)][(j,d)] G[(q,P)][(j,d)]
-    GemmDesc d = gd((int)N, (int)kX, (int)N, 0, N, 1, N, X);
+    GemmDesc d = gd((int)N, (int)kX, (int)N, 0, t.ldtau, 1, t.ldG, X);
     d.cRn = X;
     d.cSn = N * X;
     const int ev = e.tape ? -1 : c.events.start(s);
@@ -589,14 +633,26 @@ void contract(Context& c, const Ops<T>& t, Emit<T>& e, int order, int k, const T
     const int ib = c.strip_rows;
     for (int i0 = 0; i0 < o; i0 += ib) {
       const int nb = std::min(ib, o - i0);
-      e.gemm(gd(nb * v, (int)N, X, 1, N, 0, N, N), one, t.Bov + (size_t)i0 * v, t.Bov, zero, t.S, c.ws);
+      if (t.sbf) {
+        // (kx|ly) of the strip rows from the split transposed B^ov (rows of X8 values)
+        const long lx = c.X8;
+        e.gemm(gd(nb * v, (int)N, X, 0, lx, 1, lx, N), one, t.BovT + (size_t)i0 * v * lx, t.BovT, zero, t.S, c.ws,
+               2);
+      } else {
+        e.gemm(gd(nb * v, (int)N, X, 1, N, 0, N, N), one, t.Bov + (size_t)i0 * v, t.Bov, zero, t.S, c.ws);
+      }
       {
         const T* Sst = t.S;
         T* tw = t.tau_w;
         const double *eo = c.eps_o, *evv = c.eps_v;
-        e.call([=](hipStream_t st) { tau_strip_t(Sst, o, v, i0, nb, eo, evv, tw, st); });
+        const long ldst = t.ldst;
+        const bool sbf = t.sbf;
+        e.call([=](hipStream_t st) {
+          tau_strip_t(Sst, o, v, i0, nb, eo, evv, tw, ldst, st);
+          if (sbf) split_sbf16((long)nb * v * ldst, reinterpret_cast<float*>(tw), st);
+        });
       }
-      GemmDesc d = gd(nb * v, (int)kX, (int)N, 0, N, 1, N, X);
+      GemmDesc d = gd(nb * v, (int)kX, (int)N, 0, t.ldst, 1, t.ldG, X);
       d.cRn = X;
       d.cSn = (long)nb * v * X;
       const int ev = e.tape ? -1 : c.events.start(s);
@@ -624,12 +680,13 @@ void contract(Context& c, const Ops<T>& t, Emit<T>& e, int order, int k, const T
 }  // namespace
 
 Footprint context_footprint(int o, int v, int X, int order, bool dip, bool store, int strip_rows, bool want_f32,
-                            int k) {
+                            int k, bool split) {
   // mirrors setup_context, grow_workspace and grow_workspace32 (arena blocks are
   // rounded to 256 B)
   auto r = [](size_t bytes) { return ((bytes + 255) / 256) * 256; };
   const size_t D = sizeof(double), F = sizeof(float);
   const size_t N = (size_t)o * v, K = (size_t)k;
+  const size_t N8 = (N + 7) / 8 * 8, X8 = ((size_t)X + 7) / 8 * 8;
   const size_t ns = order >= 2 ? 2 : 1;
   const int ib = order >= 2 ? std::max(1, std::min(strip_rows > 0 ? strip_rows : o, o)) : 0;
   size_t keep = r(o * D) + r(v * D) + r(X * (size_t)o * o * D) + r(X * (size_t)v * v * D) + r(ns * X * N * D);
@@ -649,7 +706,8 @@ Footprint context_footprint(int o, int v, int X, int order, bool dip, bool store
   if (want_f32 && order >= 1) {
     keep += r(ns * X * N * F) + 2 * r((size_t)X * o * o * F) + r((size_t)X * v * v * F) + r((size_t)o * ns * X * v * F);
     if (order >= 2) {
-      if (store) keep += r(N * N * F);
+      if (store) keep += r(N * (split ? N8 : N) * F);
+      if (split && !store) keep += r(N * X8 * F);
       keep += 2 * r((size_t)v * v * F) + 2 * r((size_t)o * o * F);
     }
   }
@@ -665,10 +723,10 @@ Footprint context_footprint(int o, int v, int X, int order, bool dip, bool store
     }
     if (want_f32) {
       ws += 4 * r(K * N * F) + r(4 * K * N * F);
-      ws += r(X * K * F) + r(K * X * N * F) + r(K * o * ns * X * o * F);
+      ws += r(X * K * F) + r(K * X * N8 * F) + r(K * o * ns * X * o * F);
       if (order >= 2) {
         ws += r(ibw * v * K * X * F);
-        if (!store) ws += 2 * r((size_t)ib * v * N * F);
+        if (!store) ws += r((size_t)ib * v * N * F) + r((size_t)ib * v * N8 * F);
       }
     }
   }
@@ -764,8 +822,8 @@ void pass_on_stream(Context& c, int order, int k, int prec, const double* V, dou
   const int ev_pass = c.events.start(s);
   emit_pass(c, order, k, prec, V, AV, BV, SV, s, nullptr);
   c.events.stop(ev_pass, s, 0);
-  c.stats.flops += sigma_flops(c, order, k);
-  if (prec == 1) c.stats.flops32 += sigma_flops(c, order, k);
+  c.stats.flops += sigma_flops(c, order, k, prec);
+  if (prec == 1) c.stats.flops32 += sigma_flops(c, order, k, prec);
   c.stats.vectors += k;
 }
 
@@ -789,8 +847,8 @@ int sigma_group(const std::vector<PassJob>& jobs, hipStream_t s) {
     if (pj.k <= 0) continue;
     emit_pass(*pj.c, pj.order, pj.k, pj.prec, pj.V, pj.AV, pj.BV, pj.SV, s, &tapes[j]);
     if (pj.order >= 1) {
-      pj.c->stats.flops += sigma_flops(*pj.c, pj.order, pj.k);
-      if (pj.prec == 1) pj.c->stats.flops32 += sigma_flops(*pj.c, pj.order, pj.k);
+      pj.c->stats.flops += sigma_flops(*pj.c, pj.order, pj.k, pj.prec);
+      if (pj.prec == 1) pj.c->stats.flops32 += sigma_flops(*pj.c, pj.order, pj.k, pj.prec);
       pj.c->stats.vectors += pj.k;
     }
   }

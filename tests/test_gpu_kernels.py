@@ -389,3 +389,65 @@ def test_partial_syev(B, case):
     res = np.linalg.norm(A @ Zh - Zh * w, axis=0)
     assert res.max() < 1e-10 * np.abs(lam).max(), res.max()
     np.testing.assert_allclose(Zh.T @ Zh, np.eye(q), atol=1e-10)
+
+
+def _bf16_rne(x32):
+    """float32 -> bf16 bit patterns, round to nearest even (finite inputs)."""
+    b = x32.view(np.uint32).astype(np.uint64)
+    return (((b + 0x7FFF + ((b >> 16) & 1)) >> 16) & 0xFFFF).astype(np.uint16)
+
+
+def _bf16_value(h):
+    return (h.astype(np.uint32) << 16).view(np.float32)
+
+
+def test_split_sbf16_layout(B):
+    """The split layout of the split-BF16 products, in place: every chunk of 8 float32
+    values becomes their 8 bf16 hi parts (round to nearest even) followed by the 8 bf16
+    lo parts of x - hi, and hi + lo reproduces x to 2^-16 relative; a length that is not
+    a whole number of chunks is refused."""
+    rng = np.random.default_rng(5)
+    x = (rng.standard_normal(8 * 1001) * np.exp(rng.uniform(-20, 20, 8 * 1001))).astype(np.float32)
+    x[:8] = [0.0, -0.0, 1.0, -1.0, 3.0, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -9, -(1.0 + 2.0 ** -8)]
+    d = torch.tensor(x, device="cuda")
+    B.split_sbf16(d)
+    got = d.cpu().numpy().view(np.uint16).reshape(-1, 16)
+    hi = _bf16_rne(x)
+    lo = _bf16_rne((x - _bf16_value(hi)).astype(np.float32))
+    np.testing.assert_array_equal(got[:, :8].ravel(), hi)
+    np.testing.assert_array_equal(got[:, 8:].ravel(), lo)
+    back = _bf16_value(hi).astype(np.float64) + _bf16_value(lo).astype(np.float64)
+    assert np.all(np.abs(back - x) <= 2.0 ** -16 * np.abs(x))
+    # ties go to even: 1 + 2^-8 rounds down to 1, 1 + 3 * 2^-9 up to 1 + 2^-7
+    assert _bf16_value(hi[5:7]).tolist() == [1.0, 1.0 + 2.0 ** -7]
+    with pytest.raises(B.PPError):
+        B.split_sbf16(torch.zeros(12, dtype=torch.float32, device="cuda"))
+
+
+@pytest.mark.parametrize("shape", [(256, 256, 4096), (200, 300, 1000)])
+def test_gemm_split_bf16_presplit(B, shape):
+    """The split-BF16 kernel on operands split in place (rows padded to 8 values with
+    zeros): the same result as the path that splits copies, bit for bit, and within the
+    split's error of the float64 product; leading dimensions that are not whole chunks
+    are refused."""
+    M, N, K = shape
+    ld = (K + 7) // 8 * 8
+    rng = np.random.default_rng(M * 3 + K)
+    A = np.zeros((M, ld), np.float32)
+    Bt = np.zeros((N, ld), np.float32)
+    A[:, :K] = rng.standard_normal((M, K))
+    Bt[:, :K] = rng.standard_normal((N, K))
+    dA, dB = torch.tensor(A, device="cuda"), torch.tensor(Bt, device="cuda")
+    ref_c = torch.empty((M, N), dtype=torch.float32, device="cuda")
+    B.gemm(dA, dB, ref_c, M=M, N=N, K=K, transA=0, lda=ld, transB=1, ldb=ld, ldc=N, fp32=2)
+    B.split_sbf16(dA)
+    B.split_sbf16(dB)
+    dC = torch.empty((M, N), dtype=torch.float32, device="cuda")
+    B.gemm(dA, dB, dC, M=M, N=N, K=K, transA=0, lda=ld, transB=1, ldb=ld, ldc=N, fp32=3)
+    assert torch.equal(dC, ref_c)
+    ref = A[:, :K].astype(np.float64) @ Bt[:, :K].astype(np.float64).T
+    err = np.abs(dC.double().cpu().numpy() - ref).max()
+    assert err <= 1e-5 * np.sqrt(K) * np.abs(A).max() * np.abs(Bt).max(), err
+    if K % 8:
+        with pytest.raises(B.PPError):
+            B.gemm(dA, dB, dC, M=M, N=N, K=K, transA=0, lda=K, transB=1, ldb=K, ldc=N, fp32=3)

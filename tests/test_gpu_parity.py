@@ -207,18 +207,24 @@ def test_fp32_products_within_single_precision(P):
         assert err <= 2e-6 * np.abs(corr).max() + 1e-14, (j, err, np.abs(corr).max())
 
 
-def test_split_bf16_products(P):
+@pytest.mark.parametrize("name", ["mid", "ragged"])
+@pytest.mark.parametrize("store", [1, 0])
+def test_split_bf16_products(P, name, store):
     """Split-BF16 amplitude contraction (FP32 elsewhere, FP64 diagonal and assembly): the
     products agree with the oracle to the split's accuracy, a relative 2^-16 per product,
-    on the parts beyond the diagonal."""
+    on the parts beyond the diagonal; amplitudes stored or rebuilt in strips (then their
+    integrals are split-BF16 products too), on a system whose particle-hole dimension and
+    auxiliary size are whole 8-value chunks and on one where neither is."""
     torch = pytest.importorskip("torch")
-    sys = _sys("mid")
+    sys = _sys(name)
+    print(f"[sbf16 products] system={name} store={store} N={sys.N} naux={sys.naux}", flush=True)
     X = random_block(5, sys.N, 2)
     V = torch.tensor(np.concatenate([X[:, 0], X[:, 1]]), dtype=torch.float64, device="cuda")
     outs = [torch.empty_like(V) for _ in range(3)]
     A, B, S = dense.assemble(sys, 2)
     A1, B1, _ = dense.assemble(sys, 1)
-    with P.Handle.from_system(sys, order=2, precision=P.PP_SPLIT_BF16) as h:
+    with P.Handle.from_system(sys, order=2, precision=P.PP_SPLIT_BF16, store_amplitudes=store,
+                              strip_rows=3) as h:
         h.products(V, outs[0], outs[1], outs[2], fp32=True)
     Vh = V.cpu().numpy()
     ref = [(A @ Vh.T).T, (B @ Vh.T).T, (S @ Vh.T).T]
