@@ -76,6 +76,9 @@ typedef enum {
 #define PP_APPLY_METRIC 1u  /* return Sigma X instead of M X */
 #define PP_DEVICE_PTRS 2u   /* X and out are device pointers */
 #define PP_ASYNC 4u         /* return once the product is enqueued (with PP_DEVICE_PTRS only) */
+#define PP_REDUCED 8u       /* contractions in the handle's reduced precision (opt->precision PP_FP32
+                               or PP_SPLIT_BF16 at setup; PP_ENOTSUP on an FP64 handle); the
+                               orbital-energy terms and the final combination stay FP64 */
 
 typedef struct pp_handle pp_handle;
 
@@ -152,7 +155,8 @@ pp_status pp_setup(const pp_system* sys, const pp_options* opt, pp_handle** out)
 
 /* out = M X (or Sigma X with PP_APPLY_METRIC) for m 2N-vectors.  X and out are
  * [m][2][n_occ][n_vir]; order (0..2) must not exceed the setup order.  The
- * handle's FP64 path is used.  Synchronous, unless PP_ASYNC (which needs
+ * contractions run in FP64, or with PP_REDUCED in the handle's reduced precision.
+ * Synchronous, unless PP_ASYNC (which needs
  * PP_DEVICE_PTRS): the call then returns once the work is enqueued on the
  * handle's stream (opt->stream, or the stream the handle owns).  X must stay
  * unchanged and out unread until that work is done: work the caller orders after
@@ -160,6 +164,24 @@ pp_status pp_setup(const pp_system* sys, const pp_options* opt, pp_handle** out)
  * first).  Asynchronous calls keep their staging buffers (4 * 2m * N doubles for
  * the largest m so far) in the handle until pp_destroy. */
 pp_status pp_sigma(pp_handle* h, int32_t order, int32_t m, const double* X, double* out, uint32_t flags);
+
+/* The product of pp_sigma issued as n_parts calls, for passes too long to issue at
+ * once: at second order the amplitudes are rebuilt in occupied strips in every pass (the
+ * matrix-free product of the second-order equations), and at n_occ = 256, n_vir = 1024,
+ * n_aux = 4096 one pass over 16 vectors is about 1e16 flops.  Part p multiplies the
+ * amplitude strips of occupied rows [n_occ p / n_parts, n_occ (p + 1) / n_parts); part 0
+ * also runs every contraction that does not depend on the strips (the first-order terms,
+ * G = V B^vv - B^oo V, the delta-type second-order terms; with stored amplitudes the whole
+ * amplitude contraction), and the last part the final combination, after which out holds
+ * M X (or Sigma X).  Call parts 0 .. n_parts - 1 in order with the arguments of part 0;
+ * X must stay unchanged and out unread until the last part is done.  The handle keeps
+ * the pass's intermediates and staging (4 * 2m * N doubles) between parts and frees them
+ * after the last.  Flags as pp_sigma (PP_ASYNC: each part returns once enqueued).
+ * PP_EINVAL for n_parts outside 1..n_occ, a part out of order or with other arguments, or
+ * a part after another product ran on the handle (the pass must start again at part 0);
+ * otherwise as pp_sigma. */
+pp_status pp_sigma_part(pp_handle* h, int32_t order, int32_t m, const double* X, double* out, uint32_t flags,
+                        int32_t part, int32_t n_parts);
 
 /* Waits until every product enqueued on the handle with PP_ASYNC is done. */
 pp_status pp_sync(pp_handle* h);

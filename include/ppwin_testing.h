@@ -25,7 +25,8 @@ extern "C" {
  * batch or outer reduction, else PP_EINVAL; the operands are copied into zero-padded
  * rows of a multiple of 8 values and split there, as the library does with its own),
  * fp32 = 3 the split-BF16 kernel on operands already in the split layout of
- * ppint_split_sbf16 (lda, ldb multiples of 8 and >= K, 16-byte aligned, else PP_EINVAL).
+ * ppint_split_sbf16 (lda, ldb multiples of 8 and >= K, 16-byte aligned, else PP_EINVAL),
+ * fp32 = 4 and 5 the same with its 128 x 128 or 256 x 256 tiles forced (for M, N >= 96).
  * ws_bytes of scratch are allocated for split-K (0 = no split). */
 pp_status ppint_gemm(int32_t fp32, int32_t M, int32_t N, int32_t K, int32_t KB, int32_t nbatch, int32_t transA,
                      int64_t lda, int64_t sA, int64_t sAk, int32_t transB, int64_t ldb, int64_t sB, int64_t sBk,

@@ -179,7 +179,7 @@ def assemble(sys, order: int):
     return A, B, S
 
 
-def b2_dense(sys, tau):
+def b2_dense(sys, tau, ladder: str = "auto"):
     """Second-order B block, element form, [i,a,j,b].
 
     B2_{ia,jb} = sum_cd (ac|bd) tau_ij^cd            pp ladder
@@ -188,10 +188,16 @@ def b2_dense(sys, tau):
                - sum_kc (kj|ac) tau_ik^cb            ring (exchange-type)
                - sum_kc (kc|bi) tau_jk^ac            ring (Coulomb-type)
                - sum_kc (kc|aj) tau_ik^bc            ring (Coulomb-type)
+
+    The pp ladder is taken either through the (ac|bd) array ("eri", v^4 storage) or
+    factor by factor, sum_P B_P,ac tau_ij^cd B_P,bd ("per_P", for large v); "auto"
+    chooses by the size of (ac|bd).
     """
     o, v, naux = sys.o, sys.v, sys.naux
+    if ladder not in ("auto", "eri", "per_P"):
+        raise ValueError("ladder must be 'auto', 'eri' or 'per_P'")
     # pp ladder via the DF factors: sum_P (B_P tau_ij B_P)_ab
-    if v ** 4 * 8 <= 6e9:
+    if ladder == "eri" or (ladder == "auto" and v ** 4 * 8 <= 6e9):
         vvvv = eri_vvvv(sys)                                        # (ac|bd) = [a,c,b,d]
         ladder_pp = np.einsum("acbd,ijcd->iajb", vvvv, tau, optimize=True)
     else:

@@ -22,6 +22,7 @@ PP_FOLDED, PP_RIESZ = 0, 1
 PP_APPLY_METRIC = 1
 PP_DEVICE_PTRS = 2
 PP_ASYNC = 4
+PP_REDUCED = 8
 PP_MAX_ROOTS = 64
 
 
@@ -117,6 +118,8 @@ def lib() -> C.CDLL:
         L.pp_mp2_energy.restype = dbl
         L.pp_device_bytes.argtypes = [vp]
         L.pp_device_bytes.restype = u64
+        L.pp_sigma_part.argtypes = [vp, i32, i32, vp, vp, u32, i32, i32]
+        L.pp_sigma_part.restype = C.c_int
         L.pp_sync.argtypes = [vp]
         L.pp_sync.restype = C.c_int
         L.pp_destroy.argtypes = [vp]
@@ -243,22 +246,40 @@ class Handle:
     def __exit__(self, *a):
         self.close()
 
-    def sigma(self, X, order: Optional[int] = None, metric: bool = False) -> np.ndarray:
-        """M X (or Sigma X) for host X of shape [m][2][o][v] or [m][2][N]."""
+    def sigma(self, X, order: Optional[int] = None, metric: bool = False, reduced: bool = False) -> np.ndarray:
+        """M X (or Sigma X) for host X of shape [m][2][o][v] or [m][2][N]; reduced=True runs
+        the contractions in the handle's reduced precision (PP_REDUCED)."""
         X = _f64(X)
         m = X.shape[0]
         out = np.empty((m, 2, self.N))
-        st = lib().pp_sigma(self.h, self.order if order is None else order, m, X.ctypes.data, out.ctypes.data,
-                            PP_APPLY_METRIC if metric else 0)
+        flags = (PP_APPLY_METRIC if metric else 0) | (PP_REDUCED if reduced else 0)
+        st = lib().pp_sigma(self.h, self.order if order is None else order, m, X.ctypes.data, out.ctypes.data, flags)
         _check(st, self.h)
         return out
 
-    def sigma_device(self, X, out, order: Optional[int] = None, metric: bool = False, async_: bool = False):
+    def sigma_device(self, X, out, order: Optional[int] = None, metric: bool = False, async_: bool = False,
+                     reduced: bool = False):
         """Same as sigma() on torch device tensors (no host copies).  async_=True returns
         once the product is enqueued on the handle's stream (see sync())."""
         m = X.shape[0]
-        flags = PP_DEVICE_PTRS | (PP_APPLY_METRIC if metric else 0) | (PP_ASYNC if async_ else 0)
+        flags = (PP_DEVICE_PTRS | (PP_APPLY_METRIC if metric else 0) | (PP_ASYNC if async_ else 0)
+                 | (PP_REDUCED if reduced else 0))
         st = lib().pp_sigma(self.h, self.order if order is None else order, m, X.data_ptr(), out.data_ptr(), flags)
+        _check(st, self.h)
+
+    def sigma_part(self, X, out, part: int, n_parts: int, order: Optional[int] = None, metric: bool = False,
+                   reduced: bool = False, async_: bool = False):
+        """One part of a product pass issued in parts (pp_sigma_part).  X, out: torch device
+        tensors [m][2][N] (device pointers) or numpy arrays (host pointers, out filled after
+        the last part)."""
+        dev = hasattr(X, "data_ptr")
+        m = X.shape[0]
+        flags = ((PP_DEVICE_PTRS if dev else 0) | (PP_APPLY_METRIC if metric else 0) | (PP_ASYNC if async_ else 0)
+                 | (PP_REDUCED if reduced else 0))
+        xp = X.data_ptr() if dev else X.ctypes.data
+        op = out.data_ptr() if dev else out.ctypes.data
+        st = lib().pp_sigma_part(self.h, self.order if order is None else order, m, xp, op, flags, int(part),
+                                 int(n_parts))
         _check(st, self.h)
 
     def sync(self):

@@ -21,6 +21,18 @@ struct pp_handle {
   double* abuf = nullptr;
   size_t acap = 0;     // doubles per buffer
   bool pending = false;  // asynchronous work may still be running on the handle's stream
+  // a product pass issued in parts (pp_sigma_part): its arguments, staging (V, AV, BV, SV
+  // and, for host output, out) and the next part expected
+  struct Parts {
+    int next = -1;  // -1: no pass in progress
+    int order = 0, m = 0, n_parts = 0;
+    const double* X = nullptr;
+    double* out = nullptr;
+    uint32_t flags = 0;
+    long serial = 0;
+    double* buf = nullptr;
+    double* dout = nullptr;
+  } parts;
 };
 
 namespace {
@@ -39,6 +51,21 @@ void settle(pp_handle* h) {
     PPW_HIP(hipStreamSynchronize(h->ctx->stream));
     h->pending = false;
   }
+}
+
+// Drops the staging of a pass issued in parts (after its work is settled).
+void drop_parts(pp_handle* h) {
+  if (h->parts.buf) h->ctx->arena.free(h->parts.buf);
+  if (h->parts.dout) h->ctx->arena.free(h->parts.dout);
+  h->parts = pp_handle::Parts{};
+}
+
+// Precision of the contractions a product call asks for (PP_REDUCED: the handle's).
+int product_precision(const pp_handle* h, uint32_t flags) {
+  if (!(flags & PP_REDUCED)) return 0;
+  if (h->opt.precision == PP_FP64)
+    throw ppw::NotSupported("PP_REDUCED needs a handle set up with PP_FP32 or PP_SPLIT_BF16");
+  return 1;
 }
 }  // namespace
 
@@ -125,6 +152,7 @@ pp_status pp_sigma(pp_handle* h, int32_t order, int32_t m, const double* X, doub
     const bool dev = (flags & PP_DEVICE_PTRS) != 0;
     const bool async = (flags & PP_ASYNC) != 0;
     if (async && !dev) throw ppw::InvalidArg("PP_ASYNC needs PP_DEVICE_PTRS");
+    (void)product_precision(h, flags);
     const int k = 2 * m;
     const size_t per = (size_t)k * N;
     struct Free {
@@ -171,7 +199,7 @@ pp_status pp_sigma(pp_handle* h, int32_t order, int32_t m, const double* X, doub
     PPW_HIP(hipMemcpy2DAsync(V + (size_t)m * N, N * sizeof(double), X + N, 2 * N * sizeof(double),
                              N * sizeof(double), m, kin, c.stream));
     const bool metric = (flags & PP_APPLY_METRIC) != 0;
-    ppw::sigma_core(c, order, k, V, AV, BV, SV);
+    ppw::sigma_pass(c, order, k, product_precision(h, flags), V, AV, BV, SV, ppw::PassRange{});
     ppw::combine_pairs(N, m, AV, BV, SV, metric, out, c.stream);
     if (!dev)
       PPW_HIP(hipMemcpyAsync(outp, out, sizeof(double) * 2 * m * N, hipMemcpyDeviceToHost, c.stream));
@@ -180,6 +208,83 @@ pp_status pp_sigma(pp_handle* h, int32_t order, int32_t m, const double* X, doub
       return;
     }
     PPW_HIP(hipStreamSynchronize(c.stream));
+  });
+}
+
+pp_status pp_sigma_part(pp_handle* h, int32_t order, int32_t m, const double* X, double* outp, uint32_t flags,
+                        int32_t part, int32_t n_parts) {
+  if (!h || !h->ctx) return PP_EINVAL;
+  return guarded(&h->err, [&] {
+    ppw::Context& c = *h->ctx;
+    pp_handle::Parts& ps = h->parts;
+    if (n_parts < 1 || n_parts > c.o) throw ppw::InvalidArg("n_parts must be in 1..n_occ");
+    if (part < 0 || part >= n_parts) throw ppw::InvalidArg("part must be in 0..n_parts-1");
+    if (m < 1) throw ppw::InvalidArg("m must be >= 1");
+    if (order < 0 || order > c.order) throw ppw::InvalidArg("order exceeds the setup order");
+    if (!X || !outp) throw ppw::InvalidArg("NULL vector pointer");
+    const bool dev = (flags & PP_DEVICE_PTRS) != 0;
+    const bool async = (flags & PP_ASYNC) != 0;
+    if (async && !dev) throw ppw::InvalidArg("PP_ASYNC needs PP_DEVICE_PTRS");
+    const int prec = product_precision(h, flags);
+    PPW_HIP(hipSetDevice(c.device));
+    const long N = c.N;
+    const int k = 2 * m;
+    const size_t per = (size_t)k * N;
+    if (part == 0) {
+      settle(h);
+      drop_parts(h);
+      ps.buf = c.arena.alloc<double>(4 * per, "sigma part staging");
+      if (!dev) ps.dout = c.arena.alloc<double>((size_t)2 * m * N, "sigma part out");
+      ps.order = order;
+      ps.m = m;
+      ps.n_parts = n_parts;
+      ps.X = X;
+      ps.out = outp;
+      ps.flags = flags;
+    } else {
+      if (ps.next < 0) throw ppw::InvalidArg("no product pass in parts is in progress: start at part 0");
+      if (part != ps.next || order != ps.order || m != ps.m || n_parts != ps.n_parts || X != ps.X ||
+          outp != ps.out || flags != ps.flags)
+        throw ppw::InvalidArg("parts of a pass must come in order with the arguments of its part 0");
+      if (c.pass_serial != ps.serial) {
+        settle(h);
+        drop_parts(h);
+        throw ppw::InvalidArg("another product ran on the handle since part 0: start the pass again");
+      }
+    }
+    double* V = ps.buf;
+    double* AV = V + per;
+    double* BV = AV + per;
+    double* SV = BV + per;
+    if (part == 0) {
+      const hipMemcpyKind kin = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+      PPW_HIP(hipMemcpy2DAsync(V, N * sizeof(double), X, 2 * N * sizeof(double), N * sizeof(double), m, kin,
+                               c.stream));
+      PPW_HIP(hipMemcpy2DAsync(V + (size_t)m * N, N * sizeof(double), X + N, 2 * N * sizeof(double),
+                               N * sizeof(double), m, kin, c.stream));
+    }
+    ppw::PassRange rg;
+    rg.pre = part == 0;
+    rg.post = part == n_parts - 1;
+    rg.i0 = (int)((long)c.o * part / n_parts);
+    rg.i1 = (int)((long)c.o * (part + 1) / n_parts);
+    ppw::sigma_pass(c, order, k, prec, V, AV, BV, SV, rg);
+    if (rg.post) {
+      double* out = dev ? outp : ps.dout;
+      ppw::combine_pairs(N, m, AV, BV, SV, (flags & PP_APPLY_METRIC) != 0, out, c.stream);
+      if (!dev) PPW_HIP(hipMemcpyAsync(outp, out, sizeof(double) * 2 * m * N, hipMemcpyDeviceToHost, c.stream));
+    }
+    ps.serial = c.pass_serial;
+    ps.next = rg.post ? -1 : part + 1;
+    if (async) {
+      h->pending = true;
+    } else {
+      PPW_HIP(hipStreamSynchronize(c.stream));
+    }
+    if (rg.post) {
+      // the staging may still be read by enqueued work: keep it until that is settled
+      if (!async) drop_parts(h);
+    }
   });
 }
 
@@ -261,6 +366,7 @@ pp_status pp_destroy(pp_handle* h) {
       settle(h);
       if (h->abuf) h->ctx->arena.free(h->abuf);
       h->abuf = nullptr;
+      drop_parts(h);
     }
     delete h->ctx;
     h->ctx = nullptr;
@@ -421,8 +527,10 @@ pp_status ppint_gemm(int32_t fp32, int32_t M, int32_t N, int32_t K, int32_t KB, 
       w.ptr = ws;
       w.bytes = ws_bytes;
     }
-    if (fp32 == 3)
+    if (fp32 >= 3 && fp32 <= 5) {
+      d.tile = fp32 == 4 ? 128 : (fp32 == 5 ? 256 : 0);
       ppw::gemm_sbf16(d, (float)alpha, (const float*)A, (const float*)B, (float)beta, (float*)C, nullptr);
+    }
     else if (fp32 == 2)
       sbf16_from_f32(d, (float)alpha, (const float*)A, (const float*)B, (float)beta, (float*)C);
     else if (fp32)
@@ -460,8 +568,10 @@ pp_status ppint_gemm_cmap(int32_t fp32, int32_t M, int32_t N, int32_t K, int32_t
       w.ptr = ws;
       w.bytes = ws_bytes;
     }
-    if (fp32 == 3)
+    if (fp32 >= 3 && fp32 <= 5) {
+      d.tile = fp32 == 4 ? 128 : (fp32 == 5 ? 256 : 0);
       ppw::gemm_sbf16(d, (float)alpha, (const float*)A, (const float*)B, (float)beta, (float*)C, nullptr);
+    }
     else if (fp32 == 2)
       sbf16_from_f32(d, (float)alpha, (const float*)A, (const float*)B, (float)beta, (float*)C);
     else if (fp32)

@@ -96,8 +96,8 @@ void gemm_f64_hhat(const GemmDesc& d, double alpha, const double* A, const doubl
 // error about 2^-16) on operands held in the split layout of split_sbf16: operands
 // contiguous along k with leading dimensions a multiple of 8 values (and >= K), 16-byte
 // aligned, zero past K in a row's last chunk; no batch or outer reduction; C index splits
-// allowed.  Used for the amplitude contraction (and the amplitude strips' integrals) in
-// PP_SPLIT_BF16 mode.
+// allowed; d.tile = 128 or 256 fixes the tile shape (results do not depend on it).  Used
+// for the amplitude contraction (and the amplitude strips' integrals) in PP_SPLIT_BF16 mode.
 void gemm_sbf16(const GemmDesc& d, float alpha, const float* A, const float* B, float beta, float* C, hipStream_t s);
 // Splits n FP32 values in place (n a multiple of 8, x 16-byte aligned): each chunk of 8
 // values becomes their 8 bf16 hi parts, hi = bf16(x) rounded to nearest even, followed

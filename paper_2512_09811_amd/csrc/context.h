@@ -203,6 +203,7 @@ struct Context {
 
   SigmaStats stats;
   EventLog events;
+  long pass_serial = 0;  // product passes started on this context (a part sequence checks it)
   std::string last_error;
 
   // folds pending event timings into stats (synchronizes on them)
@@ -219,12 +220,28 @@ struct Context {
 // Builds a context (copies inputs, layouts, diagonals, MP2 intermediates).
 Context* setup_context(const SetupParams& p);
 
+// Part of a product pass: pre runs every contraction that does not depend on the
+// amplitude strips (with stored amplitudes, the amplitude contraction too), rows
+// [i0, i1) (i1 < 0: to n_occ) the strips of those occupied rows, post the final FP64
+// combination.  The parts of one pass cover the occupied rows once, pre first and post
+// last, with no other product on the context in between (they share its workspaces).
+struct PassRange {
+  bool pre = true;
+  int i0 = 0, i1 = -1;
+  bool post = true;
+};
+
 // Products of k particle-hole vectors V ([k][o][v], device): AV = A V, BV = B V,
 // SV = S V (SV may be null) at the given order (<= ctx order).  Device pointers.
 void sigma_core(Context& c, int order, int k, const double* V, double* AV, double* BV, double* SV);
 
 // Same products with the contractions on FP32 matrix cores (V and outputs FP64).
 void sigma_core_f32(Context& c, int order, int k, const double* V, double* AV, double* BV, double* SV);
+
+// One part of a product pass (prec 0: FP64 contractions; 1: the context's reduced
+// precision, FP32 or split-BF16 amplitude products) on the context's stream.
+void sigma_pass(Context& c, int order, int k, int prec, const double* V, double* AV, double* BV, double* SV,
+                const PassRange& rg);
 
 // One system's share of a merged product pass.
 struct PassJob {

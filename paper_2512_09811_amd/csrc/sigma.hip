@@ -80,8 +80,11 @@ static bool amplitudes_stored(const Context& c, int prec) {
   return c.tau != nullptr;
 }
 
-double sigma_flops(const Context& c, int order, int k, int prec) {
-  if (order <= 0) return 0.0;
+// Algorithmic flops of the part of a pass that does not depend on the amplitude strips
+// (pre) and of the strips of 'rows' occupied rows.
+static void pass_flops(const Context& c, int order, int k, int prec, int rows, double* pre, double* strips) {
+  *pre = *strips = 0.0;
+  if (order <= 0) return;
   const double o = c.o, v = c.v, X = c.naux, N = (double)c.N, K = k;
   double f = 0.0;
   f += 2.0 * X * N * K * 2.0;                  // J (two GEMMs)
@@ -90,16 +93,28 @@ double sigma_flops(const Context& c, int order, int k, int prec) {
   const double ns = order >= 2 ? 2.0 : 1.0;
   f += 2.0 * K * o * v * ns * X * o;           // V^T [B^ov; Lam]
   f += 2.0 * K * o * ns * X * o * v;           // ring / K_B output
+  double g = 0.0;
   if (order >= 2) {
     f += 2.0 * K * X * o * o * v;              // - B^oo_P V   (G)
-    f += 2.0 * N * N * K * X;                  // H = tau G    (dominant)
-    if (!amplitudes_stored(c, prec)) f += 2.0 * N * N * X;  // (ia|jb) of the rebuilt strips
-    f += 2.0 * K * X * o * v * v;              // H B^vv
-    f += 2.0 * K * X * o * o * v;              // B^oo H
     f += 2.0 * K * o * v * v * 2.0;            // V Gv, V Ev
     f += 2.0 * K * o * o * v * 2.0;            // Go V, Eo V
+    g += 2.0 * N * N * K * X;                  // H = tau G    (dominant)
+    if (!amplitudes_stored(c, prec)) g += 2.0 * N * N * X;  // (ia|jb) of the rebuilt strips
+    g += 2.0 * K * X * o * v * v;              // H B^vv
+    g += 2.0 * K * X * o * o * v;              // B^oo H
   }
-  return f;
+  *pre = f;
+  // stored amplitudes: the whole contraction runs with the prologue
+  if (order >= 2 && amplitudes_stored(c, prec))
+    *pre += g;
+  else
+    *strips = g * rows / o;
+}
+
+double sigma_flops(const Context& c, int order, int k, int prec) {
+  double pre, strips;
+  pass_flops(c, order, k, prec, c.o, &pre, &strips);
+  return pre + strips;
 }
 
 Context* setup_context(const SetupParams& p) {
@@ -493,11 +508,12 @@ struct Emit {
 // by sigma_assemble.
 template <typename T>
 void contract(Context& c, const Ops<T>& t, Emit<T>& e, int order, int k, const T* V, T* AV, T* BV, T* J, T* P1,
-              T* P2, T* P3, T* P4) {
+              T* P2, T* P3, T* P4, const PassRange& rg) {
   hipStream_t s = e.s;
   const int o = c.o, v = c.v, X = c.naux;
   const long N = c.N;
   const T one = T(1), zero = T(0), mone = T(-1);
+  if (rg.pre) {
   // J: c[P][q] = sum_ia Bov[P][ia] V[q][ia];  J[q][ia] = sum_P c[P][q] Bov[P][ia]
   e.gemm(gd(X, k, (int)N, 0, N, 1, N, k), one, t.Bov, V, zero, t.c, c.ws);
   e.gemm(gd(k, (int)N, X, 1, k, 0, N, N), one, t.c, t.Bov, zero, J, c.ws);
@@ -560,7 +576,9 @@ void contract(Context& c, const Ops<T>& t, Emit<T>& e, int order, int k, const T
       e.gemm(d, mone, t.U, t.R + (size_t)X * v, zero, BV, c.ws);
     }
   }
+  }  // rg.pre
   if (order < 2) return;
+  if (rg.pre) {
   // G_P = V Bvv_P - Boo_P V  (in place on G1)
   {
     GemmDesc d = gd(o, v, o, 0, o, 0, v, v);
@@ -578,6 +596,18 @@ void contract(Context& c, const Ops<T>& t, Emit<T>& e, int order, int k, const T
     const long n = (long)k * X * t.ldG;
     e.call([=](hipStream_t st) { split_sbf16(n, reinterpret_cast<float*>(G), st); });
   }
+  // delta-type terms: P1 = V Gv, P2 = V Ev, P3 = Go V, P4 = Eo V
+  e.gemm(gd(k * o, v, v, 0, v, 0, v, v), one, V, t.Gv, zero, P1, c.ws);
+  e.gemm(gd(k * o, v, v, 0, v, 0, v, v), one, V, t.Ev, zero, P2, c.ws);
+  {
+    GemmDesc d = gd(o, v, o, 0, o, 0, v, v);
+    d.nb1 = k;
+    d.sB1 = N;
+    d.sC1 = N;
+    e.gemm(d, one, t.Go, V, zero, P3, c.ws);
+    e.gemm(d, one, t.Eo, V, zero, P4, c.ws);
+  }
+  }  // rg.pre
   const long kX = (long)k * X;
   // H = tau G is written as [q][(i,c)][P] for the ib occupied rows i of the strip (the
   // C index split sends column (q,P) of the product to q ib v X + P), so that both outputs
@@ -619,6 +649,8 @@ void contract(Context& c, const Ops<T>& t, Emit<T>& e, int order, int k, const T
   const int hhat_tag = (sizeof(T) == sizeof(float) && c.split_bf16) ? 2 : 1;
   double hflops = 0.0;
   if (t.tau) {
+    // stored amplitudes: the whole contraction in one GEMM, with the prologue
+    if (!rg.pre) return;
     // H[q][(i,c)][P] = sum_(j,d) tau[(i,c)][(j,d)] G[(q,P)][(j,d)]
     GemmDesc d = gd((int)N, (int)kX, (int)N, 0, t.ldtau, 1, t.ldG, X);
     d.cRn = X;
@@ -631,8 +663,9 @@ void contract(Context& c, const Ops<T>& t, Emit<T>& e, int order, int k, const T
     outputs(t.H, 0, o);
   } else {
     const int ib = c.strip_rows;
-    for (int i0 = 0; i0 < o; i0 += ib) {
-      const int nb = std::min(ib, o - i0);
+    const int r1 = std::min(rg.i1 < 0 ? o : rg.i1, o);
+    for (int i0 = std::max(rg.i0, 0); i0 < r1; i0 += ib) {
+      const int nb = std::min(ib, r1 - i0);
       if (t.sbf) {
         // (kx|ly) of the strip rows from the split transposed B^ov (rows of X8 values)
         const long lx = c.X8;
@@ -664,17 +697,6 @@ void contract(Context& c, const Ops<T>& t, Emit<T>& e, int order, int k, const T
     }
   }
   c.stats.hhat_flops += hflops;
-  // delta-type terms: P1 = V Gv, P2 = V Ev, P3 = Go V, P4 = Eo V
-  e.gemm(gd(k * o, v, v, 0, v, 0, v, v), one, V, t.Gv, zero, P1, c.ws);
-  e.gemm(gd(k * o, v, v, 0, v, 0, v, v), one, V, t.Ev, zero, P2, c.ws);
-  {
-    GemmDesc d = gd(o, v, o, 0, o, 0, v, v);
-    d.nb1 = k;
-    d.sB1 = N;
-    d.sC1 = N;
-    e.gemm(d, one, t.Go, V, zero, P3, c.ws);
-    e.gemm(d, one, t.Eo, V, zero, P4, c.ws);
-  }
 }
 
 }  // namespace
@@ -744,14 +766,15 @@ void sigma_reserve(Context& c, int k, int precision) {
 namespace {
 
 void emit_products(Context& c, int order, int k, int prec, const double* V, double* AV, double* BV, double* SV,
-                   hipStream_t s, std::vector<Step>* tape);
+                   hipStream_t s, std::vector<Step>* tape, const PassRange& rg);
 
 // One product pass of k vectors (contractions in the given precision, then the FP64
-// diagonal term and combination), launched on s or recorded on a tape.
+// diagonal term and combination), launched on s or recorded on a tape; rg selects the
+// part of the pass.
 void emit_pass(Context& c, int order, int k, int prec, const double* V, double* AV, double* BV, double* SV,
-               hipStream_t s, std::vector<Step>* tape) {
-  emit_products(c, order, k, prec, V, AV, BV, SV, s, tape);
-  if (c.tda) {
+               hipStream_t s, std::vector<Step>* tape, const PassRange& rg = PassRange{}) {
+  emit_products(c, order, k, prec, V, AV, BV, SV, s, tape, rg);
+  if (c.tda && rg.post) {
     // Tamm-Dancoff: B = 0
     Emit<double> em;
     em.s = s;
@@ -762,11 +785,12 @@ void emit_pass(Context& c, int order, int k, int prec, const double* V, double* 
 }
 
 void emit_products(Context& c, int order, int k, int prec, const double* V, double* AV, double* BV, double* SV,
-                   hipStream_t s, std::vector<Step>* tape) {
+                   hipStream_t s, std::vector<Step>* tape, const PassRange& rg) {
   const int o = c.o, v = c.v;
   const long N = c.N, kN = (long)k * N;
   const double *eo = c.eps_o, *ev = c.eps_v;
   if (order == 0) {
+    if (!rg.post) return;
     Emit<double> em;
     em.s = s;
     em.tape = tape;
@@ -786,8 +810,9 @@ void emit_products(Context& c, int order, int k, int prec, const double* V, doub
     em.s = s;
     em.tape = tape;
     float *V32 = c.w32_V, *AV32 = c.w32_AV, *BV32 = c.w32_BV, *J32 = c.w32_J, *P32 = c.w32_P;
-    em.call([=](hipStream_t st) { to_f32(kN, V, V32, st); });
-    contract<float>(c, ops32(c), em, order, k, V32, AV32, BV32, J32, P32, P32 + kN, P32 + 2 * kN, P32 + 3 * kN);
+    if (rg.pre) em.call([=](hipStream_t st) { to_f32(kN, V, V32, st); });
+    contract<float>(c, ops32(c), em, order, k, V32, AV32, BV32, J32, P32, P32 + kN, P32 + 2 * kN, P32 + 3 * kN, rg);
+    if (!rg.post) return;
     // the diagonal (orbital-energy) term and the combination stay in FP64
     em.call([=](hipStream_t st) {
       to_f64(kN, AV32, AV, st);
@@ -803,41 +828,56 @@ void emit_products(Context& c, int order, int k, int prec, const double* V, doub
     Emit<double> em;
     em.s = s;
     em.tape = tape;
-    contract<double>(c, ops64(c), em, order, k, V, AV, BV, J, Q1, Q1 + kN, Q1 + 2 * kN, Q1 + 3 * kN);
+    contract<double>(c, ops64(c), em, order, k, V, AV, BV, J, Q1, Q1 + kN, Q1 + 2 * kN, Q1 + 3 * kN, rg);
+    if (!rg.post) return;
     em.call([=](hipStream_t st) {
       sigma_assemble(o, v, k, order, eo, ev, V, J, Q1, Q1 + kN, Q1 + 2 * kN, Q1 + 3 * kN, AV, BV, SV, st);
     });
   }
 }
 
-void pass_on_stream(Context& c, int order, int k, int prec, const double* V, double* AV, double* BV, double* SV) {
+void pass_on_stream(Context& c, int order, int k, int prec, const double* V, double* AV, double* BV, double* SV,
+                    const PassRange& rg) {
   if (order > c.order) throw InvalidArg("requested order exceeds the setup order");
   if (k <= 0) return;
   hipStream_t s = c.stream;
+  if (rg.pre) ++c.pass_serial;
   if (order == 0) {
-    emit_pass(c, 0, k, prec, V, AV, BV, SV, s, nullptr);
+    emit_pass(c, 0, k, prec, V, AV, BV, SV, s, nullptr, rg);
     return;
   }
   if (c.events.pending() > 4096) c.resolve_stats();
   const int ev_pass = c.events.start(s);
-  emit_pass(c, order, k, prec, V, AV, BV, SV, s, nullptr);
+  emit_pass(c, order, k, prec, V, AV, BV, SV, s, nullptr, rg);
   c.events.stop(ev_pass, s, 0);
-  c.stats.flops += sigma_flops(c, order, k, prec);
-  if (prec == 1) c.stats.flops32 += sigma_flops(c, order, k, prec);
-  c.stats.vectors += k;
+  const int r0 = std::max(rg.i0, 0), r1 = std::min(rg.i1 < 0 ? c.o : rg.i1, c.o);
+  double pre, strips;
+  pass_flops(c, order, k, prec, std::max(0, r1 - r0), &pre, &strips);
+  const double f = (rg.pre ? pre : 0.0) + strips;
+  c.stats.flops += f;
+  if (prec == 1) c.stats.flops32 += f;
+  if (rg.pre) c.stats.vectors += k;
 }
 
 }  // namespace
 
 void sigma_core(Context& c, int order, int k, const double* V, double* AV, double* BV, double* SV) {
-  pass_on_stream(c, order, k, 0, V, AV, BV, SV);
+  pass_on_stream(c, order, k, 0, V, AV, BV, SV, PassRange{});
 }
 
 void sigma_core_f32(Context& c, int order, int k, const double* V, double* AV, double* BV, double* SV) {
-  pass_on_stream(c, order, k, 1, V, AV, BV, SV);
+  pass_on_stream(c, order, k, 1, V, AV, BV, SV, PassRange{});
+}
+
+void sigma_pass(Context& c, int order, int k, int prec, const double* V, double* AV, double* BV, double* SV,
+                const PassRange& rg) {
+  if (prec == 1 && !c.BovLam32 && order >= 1) throw NotSupported("reduced-precision products need a handle set up "
+                                                                 "with PP_FP32 or PP_SPLIT_BF16");
+  pass_on_stream(c, order, k, prec, V, AV, BV, SV, rg);
 }
 
 int sigma_group(const std::vector<PassJob>& jobs, hipStream_t s) {
+  for (const PassJob& pj : jobs) ++pj.c->pass_serial;
   std::vector<std::vector<Step>> tapes(jobs.size());
   for (size_t j = 0; j < jobs.size(); ++j) {
     const PassJob& pj = jobs[j];

@@ -451,3 +451,29 @@ def test_gemm_split_bf16_presplit(B, shape):
     if K % 8:
         with pytest.raises(B.PPError):
             B.gemm(dA, dB, dC, M=M, N=N, K=K, transA=0, lda=K, transB=1, ldb=K, ldc=N, fp32=3)
+
+
+@pytest.mark.parametrize("shape", [(4000, 8000, 333), (512, 768, 2048)])
+def test_gemm_split_bf16_tiles(B, shape):
+    """The split-BF16 kernel's 128 x 128 and 256 x 256 tiles (and the shape-chosen one)
+    give bit-identical products: every element sums the same 16-value steps in the same
+    order, hi-lo, lo-hi, hi-hi; ragged edges in m, n and k; within the split's error of
+    the float64 product."""
+    M, N, K = shape
+    ld = (K + 7) // 8 * 8
+    g = torch.Generator(device="cuda").manual_seed(K)
+    dA = torch.zeros((M, ld), dtype=torch.float32, device="cuda")
+    dB = torch.zeros((N, ld), dtype=torch.float32, device="cuda")
+    dA[:, :K] = torch.randn((M, K), generator=g, device="cuda")
+    dB[:, :K] = torch.randn((N, K), generator=g, device="cuda")
+    ref = (dA[:, :K].double() @ dB[:, :K].double().T).cpu().numpy()
+    B.split_sbf16(dA)
+    B.split_sbf16(dB)
+    outs = []
+    for code in (3, 4, 5):
+        dC = torch.full((M, N), 3.0, dtype=torch.float32, device="cuda")
+        B.gemm(dA, dB, dC, M=M, N=N, K=K, transA=0, lda=ld, transB=1, ldb=ld, ldc=N, alpha=0.5, beta=2.0, fp32=code)
+        outs.append(dC)
+    assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
+    err = np.abs(outs[0].double().cpu().numpy() - (0.5 * ref + 6.0)).max()
+    assert err <= 1e-5 * np.sqrt(K) * 0.5 * 25.0, err

@@ -396,3 +396,62 @@ def test_riesz_window_solve_equals_definition(order, omega0, nr):
         ov = X[:, k] @ S @ X_ref[:, k] - Y[:, k] @ S @ Y_ref[:, k]
         assert abs(abs(ov) - 1.0) < 1e-8, (k, ov)
     assert it < 60
+
+
+@pytest.mark.parametrize("o,v,naux,seed,b_scale", [(5, 19, 23, 11, 0.5), (8, 24, 64, 1, 1.0)])
+def test_second_order_rows_match_dense_assembly(o, v, naux, seed, b_scale):
+    """Rows of the complete A, B, S through second order from the element form, one row
+    at a time (oracle.columns.second_order_rows, the row oracle used where no dense matrix
+    fits) equal the rows of the dense assembly (itself pinned against the brute-force Fock
+    space, P6) for every row; the MP2 densities summed one occupied index at a time equal
+    the dense ones; without the densities the B rows still come back complete."""
+    from oracle import columns
+    sys_ = gen(seed, o, v, naux, b_scale=b_scale)
+    eps = np.concatenate([sys_.eps_o, sys_.eps_v])
+    A, B, S = dense.assemble(sys_, 2)
+    A1, B1, _ = dense.assemble(sys_, 1)
+    rng = np.random.default_rng(seed)
+    V = rng.standard_normal((3, sys_.N))
+    rows = list(range(sys_.N))
+    dens = columns.mp2_densities(eps, o, v, sys_.B_ov)
+    it = dense.second_order_intermediates(sys_)
+    for key in ("Gv", "Ev", "Go", "Eo"):
+        np.testing.assert_allclose(dens[key], it[key], rtol=0, atol=1e-14 * np.abs(it[key]).max())
+    AV, BV, SV = columns.second_order_rows(eps, o, v, sys_.B_oo, sys_.B_ov, sys_.B_vv, rows, V, dens)
+    for got, M, M1 in ((AV, A, A1), (BV, B, B1), (SV, S, np.eye(sys_.N))):
+        ref = V @ M.T
+        np.testing.assert_allclose(got, ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+        second = V @ (M - M1).T
+        assert np.abs(second).max() > 1e-6 * np.abs(ref).max()   # the second-order part is present
+        np.testing.assert_allclose(got - V @ M1.T, second, rtol=0, atol=1e-11 * np.abs(second).max())
+    _, BVb, _ = columns.second_order_rows(eps, o, v, sys_.B_oo, sys_.B_ov, sys_.B_vv, rows[:7], V)
+    np.testing.assert_allclose(BVb, BV[:, :7], rtol=0, atol=1e-15 * np.abs(BV).max())
+
+
+def test_b2_pp_ladder_factor_by_factor_equals_eri_form():
+    """The two forms of the pp ladder in dense.b2_dense (through (ac|bd), and factor by
+    factor for large n_vir) give the same B2."""
+    sys_ = gen(3, 4, 14, 21, b_scale=0.7)
+    tau = dense.second_order_intermediates(sys_)["tau"]
+    a = dense.b2_dense(sys_, tau, ladder="eri")
+    b = dense.b2_dense(sys_, tau, ladder="per_P")
+    np.testing.assert_allclose(a, b, rtol=0, atol=1e-14 * np.abs(a).max())
+    assert np.abs(a).max() > 0
+
+
+def test_select_window_ties_take_the_lower_root():
+    """Window selection: the n roots nearest omega0; roots equidistant from omega0 (within
+    the 1e-9 Ha resolution) go to the lower one; a root nearer by more than that wins."""
+    om = np.array([0.2, 0.4, 0.45, 0.55, 0.6, 0.9])
+    assert pencil.select_window(om, 0.5, 1).tolist() == [2]          # 0.45 and 0.55 tie -> 0.45
+    assert pencil.select_window(om, 0.5, 2).tolist() == [2, 3]
+    assert pencil.select_window(om, 0.5, 3).tolist() == [1, 2, 3]    # 0.4 and 0.6 tie -> 0.4
+    assert pencil.select_window(om, 0.5, 4).tolist() == [1, 2, 3, 4]
+    om2 = om.copy()
+    om2[3] = 0.55 + 3e-10                                             # still a tie at 1e-9
+    assert pencil.select_window(om2, 0.5, 1).tolist() == [2]
+    om2[3] = 0.55 - 2e-9                                              # nearer by 2e-9 Ha
+    assert pencil.select_window(om2, 0.5, 1).tolist() == [3]
+    # result is ascending in omega whatever the input order
+    perm = np.array([5, 3, 0, 4, 1, 2])
+    assert sorted(om[perm][pencil.select_window(om[perm], 0.5, 3)].tolist()) == [0.4, 0.45, 0.55]
