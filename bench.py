@@ -1,19 +1,28 @@
-"""Benchmark: second-order window solves on one MI355X.
+"""Benchmark: the second-order product on one MI355X.
 
-Workload (one "step"): the seeded MP2-corrected system with n_occ = 40,
-n_vir = 160, n_aux = 600 (particle-hole dimension 6,400), amplitudes stored,
-FP64 throughout.  A step runs the whole hot path on inputs already resident in
-HBM: pp_setup (layouts, MP2 densities and ring intermediate from amplitude
-strips, Jacobi diagonal), then four window solves at omega0 = 0.3, 0.6, 0.9,
-1.2 Ha with 10 roots each (energies, eigenvectors, dipole oscillator
-strengths) in one batched call (one solver thread per window, products of
-all windows merged into shared passes), then pp_destroy.  The solver runs to a
-residual tolerance of 1e-8 (--tol); results are checked against stored oracle
-values (1e-6 Ha, 1e-5 relative f) and only windows that meet both count.
+Default workload (one "step"): the largest matrix-free second-order system, n_occ =
+256, n_vir = 1024, n_aux = 4096 (particle-hole dimension 262,144, amplitudes never
+stored), inputs resident in HBM.  A product pass M X over m = 8 trial 2N-vectors (16
+particle-hole vectors: the largest batch whose FP32 intermediates fit beside the
+operands) is issued as 16 parts of 16 occupied rows (pp_sigma_part); one step is one
+part: the amplitude strips of its rows are rebuilt from B^ov and the orbital-energy
+denominators (split-BF16 integrals, FP32 strip, in-place split), multiplied into H = tau G
+(split-BF16 products) and contracted into the output, nothing hoisted.  Part 0 of every
+pass also runs the pass prologue (first-order terms, G = V B^vv - B^oo V and its split,
+delta-type terms) and the last part the FP64 assembly, so 16 steps are one whole pass.
+Precision: contractions in FP32 with the amplitude ones as split-BF16 products (the
+mixed-precision form); the FP64 path is timed beside it on the same step (8 trial
+vectors' worth of memory only allows 4 2N-vectors there), and one complete reduced pass
+is compared with the FP64 pass on the same vectors.
 
-Prints ONE JSON line (rank 0).  Extra fields: sigma TFLOP/s (all products),
-p50/p99 window latency, accuracy, roofline of the dominant kernel (the
-amplitude contraction H = tau G, FP64 MFMA) and the CPU oracle baseline.
+value = sigma-build TFLOP/s (algorithmic flops of the parts timed / wall time).  The
+40/160/600 window solves (solves/s at 1e-6 Ha against the oracle, FP64 and split-BF16,
+p50/p99 latency) are reported as extra fields.  ``--workload mp2_o40_v160_x600`` gives
+that window benchmark as its own line; ``--serve`` the serving stream; ``--riesz`` the
+Riesz-projector comparison.
+
+Prints ONE JSON line (rank 0): roofline of the dominant kernel (the amplitude
+contraction, split-BF16, priced against the BF16 peak / 3) and the CPU oracle baseline.
 """
 from __future__ import annotations
 
@@ -62,14 +71,42 @@ def hhat_traffic(flops_per_launch, precision):
     return 1024.0 * (fetch + write)
 
 
+# HBM traffic of the split-BF16 amplitude contraction of the product benchmark, per
+# launch, from two rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE,
+# KiB per dispatch) scaled by what the same counters read for a plain 1 GiB device copy
+# in the same runs (--copy-calibration); valid for the GEMM source with this digest and
+# launches of this size only (else null).
+PRODUCT_TRAFFIC = None
+
+
+def product_traffic(flops_per_launch):
+    """Calibrated HBM bytes per launch of the product benchmark's amplitude GEMM, or None."""
+    import hashlib
+    t = PRODUCT_TRAFFIC
+    if t is None:
+        return None
+    src = os.path.join(ROOT, "paper_2512_09811_amd", "csrc", "gemm.hip")
+    with open(src, "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()[:16]
+    if digest != t["gemm_sha256_16"] or abs(flops_per_launch / t["flops_per_launch"] - 1) > 1e-9:
+        return None
+    kib = 1 << 20
+    return 1024.0 * (t["fetch_kib"] * (kib / t["copy_fetch_kib"]) + t["write_kib"] * (kib / t["copy_write_kib"]))
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="mp2_o40_v160_x600")
-    ap.add_argument("--precision", choices=list(PRECISIONS), default="fp64")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="mp2_o256_v1024_x4096",
+                    help="mp2_o256_v1024_x4096: the product benchmark (default); mp2_o40_v160_x600 (or another "
+                         "workload with stored oracle values): window solves")
+    ap.add_argument("--precision", choices=list(PRECISIONS), default=None,
+                    help="product benchmark: sbf16 (default) or fp32; window solves: fp64 (default), fp32, sbf16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-windows", action="store_true",
+                    help="product benchmark: skip the 40/160/600 window solves reported beside it")
     ap.add_argument("--tol", type=float, default=1e-8,
                     help="solver residual tolerance; every timed window is still checked against the oracle "
                          "(1e-6 Ha, 1e-5 relative f) and only windows that pass count")
@@ -273,24 +310,14 @@ def serve_main(args):
     print(json.dumps(line), flush=True)
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
-                                   "described but not implemented)"}))
-        sys.exit(2)
-    if args.riesz:
-        riesz_main(args)
-        return
-    if args.serve:
-        serve_main(args)
-        return
+def windows_run(args, name, precision_name, steps, warmup, cpu):
+    """Window solves of one workload (all its windows in one batched call per step: setup,
+    solves, teardown), checked against the stored oracle values; returns the JSON line."""
     import torch
     import paper_2512_09811_amd as P
     from synth.gen import CONFIGS, WINDOWS, gen_config
 
     P.lib()
-    name = args.workload
     cfg = CONFIGS[name]
     omegas, nr = WINDOWS[name]
     if args.windows:
@@ -300,7 +327,7 @@ def main():
     t = {k: torch.tensor(getattr(sys_, k), dtype=torch.float64, device=dev).contiguous()
          for k in ("eps", "B_oo", "B_ov", "B_vv", "dip")}
     torch.cuda.synchronize()
-    precision = PRECISIONS[args.precision]
+    precision = PRECISIONS[precision_name]
     golden_path = os.path.join(ROOT, "tests", "golden", f"{name}.json")
     golden = json.load(open(golden_path)) if os.path.exists(golden_path) else None
 
@@ -321,12 +348,12 @@ def main():
             record.append((res, st))
         return res
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step(None)
     torch.cuda.synchronize()
     recs = []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         step(recs)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -354,9 +381,9 @@ def main():
             max_de, max_df = max(max_de, de), max(max_df, df)
             if de <= 1e-6 and df <= 1e-5 and dfs <= 1e-9 and info["status"] == P.PP_OK:
                 ok += 1
-    n_windows = len(omegas) * args.steps
+    n_windows = len(omegas) * steps
     value = ok / elapsed if golden is not None else n_windows / elapsed
-    peak = {"fp64": PEAK_FP64_MFMA_TFLOPS, "fp32": PEAK_FP32_MFMA_TFLOPS, "sbf16": PEAK_SPLIT_BF16_TFLOPS}[args.precision]
+    peak = {"fp64": PEAK_FP64_MFMA_TFLOPS, "fp32": PEAK_FP32_MFMA_TFLOPS, "sbf16": PEAK_SPLIT_BF16_TFLOPS}[precision_name]
     achieved = (h_flops / h_sec) / 1e12 if h_sec > 0 else 0.0
     # algorithmic bytes of one launch: tau (N x N) read once, G read and H written once
     kX = (h_flops / max(h_n, 1)) / (2.0 * cfg["o"] * cfg["v"] * cfg["o"] * cfg["v"])
@@ -367,13 +394,13 @@ def main():
         "value": value,
         "unit": "solves/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": 1e3 * elapsed / steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": DTYPES[args.precision],
+        "dtype": DTYPES[precision_name],
         "data": "synthetic (seeded generator; PbS/CdS orbitals and integrals are not available)",
         "config": {"workload": f"{name}: second-order, n_occ={cfg['o']}, n_vir={cfg['v']}, n_aux={cfg['naux']}, "
                                f"{len(omegas)} windows x {nr} roots, amplitudes stored",
@@ -390,16 +417,16 @@ def main():
         "roofline": {"bound": "mfma",
                      "kernel": ("gemm_kernel<double,128,128,16,1> (H = tau G; a call is the main launch plus a "
                                 "peeled 64x64 tail when its last wave would run at most half full)"
-                                if args.precision == "fp64" else
+                                if precision_name == "fp64" else
                                 "gemm_kernel<float,128,128,16,1> and its FP64 refinement passes (H = tau G), "
                                 "priced against the FP32 peak"
-                                if args.precision == "fp32" else
+                                if precision_name == "fp32" else
                                 "gemm_sbf16_kernel (split BF16, three BF16 MFMAs per product) and its FP64 "
                                 "refinement passes (H = tau G), priced against the BF16 peak / 3"),
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                      "launches": h_n, "avg_launch_ms": 1e3 * h_sec / max(h_n, 1),
                      "flops_per_launch": h_flops / max(h_n, 1),
-                     "traffic": hhat_traffic(h_flops / max(h_n, 1), args.precision),
+                     "traffic": hhat_traffic(h_flops / max(h_n, 1), precision_name),
                      "algorithmic_bytes_per_launch": hhat_bytes},
     }
     if args.copy_calibration:
@@ -411,9 +438,231 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         del x, y
-    if not args.no_cpu_baseline:
+    if cpu:
         line["cpu_baseline"] = cpu_baseline(name)
+    return line
+
+
+
+
+# The default workload: the largest matrix-free second-order system, products in parts.
+PRODUCT_WORKLOAD = "mp2_o256_v1024_x4096"
+PRODUCT_M = 8           # trial 2N-vectors per reduced-precision pass (16 particle-hole vectors)
+PRODUCT_M_FP64 = 4      # FP64 pass width (FP64 intermediates take twice the memory)
+PRODUCT_PARTS = 16      # parts per pass: 16 occupied rows each (one step = one part)
+PRODUCT_STRIP_ROWS = 8  # occupied rows per amplitude strip (two strips per part)
+
+
+def product_cpu_baseline(o, v, X, seed, k, flops_per_row):
+    """The oracle's rows of the same product on the host cores: one row of the complete
+    second-order B V and of the first-order A V for k vectors (oracle.columns, the
+    element form), from host copies of the same device-drawn inputs.  Reported in the
+    metric's unit: the algorithmic flops of the rows computed (the pass's flops per
+    particle-hole row) per second of oracle time."""
+    import torch
+    from synth.device_gen import gen_device
+    from oracle import columns
+    t = gen_device(seed, o, v, X)
+    host = {key: val.cpu().numpy() for key, val in t.items()}
+    del t
+    torch.cuda.empty_cache()
+    eps = host["eps"]
+    rng = np.random.default_rng(7)
+    V = rng.standard_normal((k, o * v))
+    row = int(rng.integers(o * v))
+    t0 = time.perf_counter()
+    columns.second_order_rows(eps, o, v, host["B_oo"], host["B_ov"], host["B_vv"], [row], V)
+    dt = time.perf_counter() - t0
+    try:
+        import threadpoolctl
+        threads = max((p.get("num_threads", 0) for p in threadpoolctl.threadpool_info()), default=0)
+    except Exception:
+        threads = 0
+    return dict(value=flops_per_row / dt / 1e12, unit="TFLOP/s", cores=int(threads or os.cpu_count()),
+                kind="oracle",
+                sample=f"one particle-hole row ({row}) of the complete second-order B V and first-order A V for "
+                       f"{k} vectors by the row oracle (element form; the delta-type A and S rows, which need the "
+                       f"MP2 densities, left out), {dt:.1f} s; scaled by the pass's algorithmic flops per row, "
+                       f"{flops_per_row:.3e}")
+
+
+def product_main(args):
+    """The default benchmark line (see the module docstring)."""
+    import torch
+    import paper_2512_09811_amd as P
+    from synth.gen import CONFIGS
+    from synth.device_gen import gen_device
+    P.lib()
+    cfg = CONFIGS[PRODUCT_WORKLOAD]
+    o, v, X, seed = cfg["o"], cfg["v"], cfg["naux"], cfg["seed"]
+    N = o * v
+    prec_name = args.precision or "sbf16"
+    if prec_name == "fp64":
+        raise SystemExit("the product benchmark's headline is the reduced-precision pass; FP64 is timed beside it")
+    budget = int(torch.cuda.get_device_properties(0).total_memory - (6 << 30))
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    def make_handle(precision):
+        t = gen_device(seed, o, v, X)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = P.Handle(t["eps"], t["B_oo"], t["B_ov"], t["B_vv"], t["dip"], order=2, device_ptrs=True,
+                     precision=precision, store_amplitudes=0, strip_rows=PRODUCT_STRIP_ROWS, hbm_budget=budget)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        del t
+        torch.cuda.empty_cache()
+        return h, dt
+
+    def vectors(m):
+        g = torch.Generator(device="cuda")
+        g.manual_seed(1234)
+        return torch.randn((m, 2, N), generator=g, device="cuda", dtype=torch.float64)
+
+    def timed_parts(h, Xv, out, reduced, warmup, steps):
+        for s_ in range(warmup):
+            h.sigma_part(Xv, out, s_ % PRODUCT_PARTS, PRODUCT_PARTS, reduced=reduced)
+        torch.cuda.synchronize()
+        h.reset_stats()
+        t0 = time.perf_counter()
+        for s_ in range(warmup, warmup + steps):
+            h.sigma_part(Xv, out, s_ % PRODUCT_PARTS, PRODUCT_PARTS, reduced=reduced)
+            log(f"{'reduced' if reduced else 'fp64'} step {s_ - warmup + 1}/{steps} (part {s_ % PRODUCT_PARTS}) "
+                f"at {time.perf_counter() - t0:.1f} s")
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, h.stats()
+
+    # reduced precision: the headline
+    h, setup_red = make_handle(PRECISIONS[prec_name])
+    log(f"{prec_name} handle set up in {setup_red:.1f} s ({h.device_bytes() / 2**30:.1f} GiB)")
+    Xv = vectors(PRODUCT_M)
+    out = torch.empty_like(Xv)
+    elapsed, st = timed_parts(h, Xv, out, True, args.warmup, args.steps)
+    X1 = vectors(1)
+    red1 = torch.empty_like(X1)
+    h.sigma_device(X1, red1, reduced=True)
+    red1 = red1.cpu().numpy()
+    h.close()
+    del Xv, out
+    torch.cuda.empty_cache()
+    value = st["product_flops"] / elapsed / 1e12
+    rows_timed = args.steps * o / PRODUCT_PARTS
+    h_n = st["hhat_launches"]
+    achieved = st["hhat_flops"] / st["hhat_seconds"] / 1e12 if st["hhat_seconds"] > 0 else 0.0
+    flops_per_launch = st["hhat_flops"] / max(h_n, 1)
+    # algorithmic bytes of one launch: the split strip [rows v][N] and G [16 naux][N] read once
+    # (4 bytes a value), H [16 naux][rows v] written once
+    strip_rows_v = PRODUCT_STRIP_ROWS * v
+    kX = 2 * PRODUCT_M * X
+    hhat_bytes = 4.0 * (strip_rows_v * N + kX * N + strip_rows_v * kX)
+    log(f"reduced: {value:.1f} TF/s over {args.steps} steps, amplitude GEMM {achieved:.1f} TF/s")
+
+    # FP64 beside it: same step, 4 trial vectors (memory), and the FP64 pass on the reduced one's vectors
+    hf, setup64 = make_handle(P.PP_FP64)
+    log(f"fp64 handle set up in {setup64:.1f} s")
+    Xf = vectors(PRODUCT_M_FP64)
+    outf = torch.empty_like(Xf)
+    fsteps = max(1, min(2, args.steps))
+    elf, stf = timed_parts(hf, Xf, outf, False, 1 if args.warmup else 0, fsteps)
+    ref1 = torch.empty_like(X1)
+    hf.sigma_device(X1, ref1)
+    first1 = torch.empty_like(X1)
+    hf.sigma_device(X1, first1, order=1)
+    ref1, first1 = ref1.cpu().numpy(), first1.cpu().numpy()
+    hf.close()
+    del Xf, outf
+    torch.cuda.empty_cache()
+    err = np.abs(red1 - ref1).max()
+    rel_total = float(err / np.abs(ref1).max())
+    rel_second = float(err / np.abs(ref1 - first1).max())
+    fp64_tflops = stf["product_flops"] / elf / 1e12
+    fp64_hhat = stf["hhat_flops"] / stf["hhat_seconds"] / 1e12 if stf["hhat_seconds"] > 0 else 0.0
+    log(f"fp64: {fp64_tflops:.1f} TF/s, amplitude GEMM {fp64_hhat:.1f} TF/s; reduced vs FP64 rel err "
+        f"{rel_total:.2e} (second-order part {rel_second:.2e})")
+
+    line = {
+        "metric": "window solves/sec + sigma-build TFLOP/s at 1e-6 Ha; p50/p99 solve latency",
+        "value": value,
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPES[prec_name],
+        "data": "synthetic (seeded device generator; PbS/CdS orbitals and integrals are not available)",
+        "config": {"workload": f"{PRODUCT_WORKLOAD}: second-order product pass M X, n_occ={o}, n_vir={v}, "
+                               f"n_aux={X}, {PRODUCT_M} trial 2N-vectors ({2 * PRODUCT_M} particle-hole vectors), "
+                               f"amplitudes rebuilt in strips of {PRODUCT_STRIP_ROWS} occupied rows, issued as "
+                               f"{PRODUCT_PARTS} parts of {o // PRODUCT_PARTS} rows; one step = one part",
+                   "parts_per_pass": PRODUCT_PARTS, "strip_rows": PRODUCT_STRIP_ROWS, "vectors": 2 * PRODUCT_M,
+                   "precision": f"{prec_name} contractions (split-BF16 amplitude products, FP32 elsewhere), "
+                                f"FP64 diagonal terms and assembly",
+                   "parallelism": "single GPU"},
+        "sigma_tflops": value,
+        "setup_seconds": setup_red,
+        "reduced_vs_fp64_max_rel_error": rel_total,
+        "reduced_vs_fp64_rel_error_of_second_order_part": rel_second,
+        "fp64_sigma_tflops": fp64_tflops,
+        "fp64_amplitude_gemm_tflops": fp64_hhat,
+        "fp64_vectors": 2 * PRODUCT_M_FP64,
+        "fp64_steps": fsteps,
+        "reduced_over_fp64": value / fp64_tflops if fp64_tflops > 0 else None,
+        "roofline": {"bound": "mfma",
+                     "kernel": "gemm_sbf16_kernel<256,256,4,2,2,1> (H = tau G of one amplitude strip: split-BF16, "
+                               "three BF16 MFMAs per FP32-equivalent product), priced against the BF16 peak / 3",
+                     "achieved": achieved, "peak": PEAK_SPLIT_BF16_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_SPLIT_BF16_TFLOPS,
+                     "launches": h_n, "avg_launch_ms": 1e3 * st["hhat_seconds"] / max(h_n, 1),
+                     "flops_per_launch": flops_per_launch,
+                     "traffic": product_traffic(flops_per_launch),
+                     "algorithmic_bytes_per_launch": hhat_bytes},
+    }
+    # the 40/160/600 window solves beside it (FP64 and the reduced precision)
+    if not args.no_windows:
+        wargs = argparse.Namespace(**vars(args))
+        wargs.copy_calibration = False
+        wargs.windows = 0
+        for pn in ("fp64", prec_name):
+            w = windows_run(wargs, "mp2_o40_v160_x600", pn, 2, 1, False)
+            line[f"windows_mp2_o40_v160_x600_{pn}"] = {
+                key: w[key] for key in ("value", "unit", "windows_meeting_tolerance", "max_abs_dE_ha", "max_rel_df",
+                                         "latency_p50_s", "latency_p99_s", "products_per_window", "sigma_tflops")}
+            line[f"windows_mp2_o40_v160_x600_{pn}"]["amplitude_gemm_tflops"] = w["roofline"]["achieved"]
+            log(f"windows {pn}: {w['value']:.2f} solves/s ({w['windows_meeting_tolerance']})")
+    if args.copy_calibration:
+        x = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = product_cpu_baseline(o, v, X, seed, 2 * PRODUCT_M, st["product_flops"] / (rows_timed * v))
     print(json.dumps(line), flush=True)
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
+                                   "described but not implemented)"}))
+        sys.exit(2)
+    if args.riesz:
+        riesz_main(args)
+        return
+    if args.serve:
+        serve_main(args)
+        return
+    if args.workload != PRODUCT_WORKLOAD:
+        line = windows_run(args, args.workload, args.precision or "fp64", args.steps, args.warmup,
+                           not args.no_cpu_baseline)
+        print(json.dumps(line), flush=True)
+        return
+    product_main(args)
 
 
 if __name__ == "__main__":
