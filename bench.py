@@ -107,6 +107,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-windows", action="store_true",
                     help="product benchmark: skip the 40/160/600 window solves reported beside it")
+    ap.add_argument("--no-fp64", action="store_true",
+                    help="product benchmark: skip the FP64 figure and the reduced-vs-FP64 check (profiling runs)")
     ap.add_argument("--tol", type=float, default=1e-8,
                     help="solver residual tolerance; every timed window is still checked against the oracle "
                          "(1e-6 Ha, 1e-5 relative f) and only windows that pass count")
@@ -540,10 +542,12 @@ def product_main(args):
     Xv = vectors(PRODUCT_M)
     out = torch.empty_like(Xv)
     elapsed, st = timed_parts(h, Xv, out, True, args.warmup, args.steps)
-    X1 = vectors(1)
-    red1 = torch.empty_like(X1)
-    h.sigma_device(X1, red1, reduced=True)
-    red1 = red1.cpu().numpy()
+    if not args.no_fp64:
+        # one complete reduced pass on a 2N-vector, compared below with the FP64 pass
+        X1 = vectors(1)
+        red1 = torch.empty_like(X1)
+        h.sigma_device(X1, red1, reduced=True)
+        red1 = red1.cpu().numpy()
     h.close()
     del Xv, out
     torch.cuda.empty_cache()
@@ -559,28 +563,31 @@ def product_main(args):
     hhat_bytes = 4.0 * (strip_rows_v * N + kX * N + strip_rows_v * kX)
     log(f"reduced: {value:.1f} TF/s over {args.steps} steps, amplitude GEMM {achieved:.1f} TF/s")
 
-    # FP64 beside it: same step, 4 trial vectors (memory), and the FP64 pass on the reduced one's vectors
-    hf, setup64 = make_handle(P.PP_FP64)
-    log(f"fp64 handle set up in {setup64:.1f} s")
-    Xf = vectors(PRODUCT_M_FP64)
-    outf = torch.empty_like(Xf)
-    fsteps = max(1, min(2, args.steps))
-    elf, stf = timed_parts(hf, Xf, outf, False, 1 if args.warmup else 0, fsteps)
-    ref1 = torch.empty_like(X1)
-    hf.sigma_device(X1, ref1)
-    first1 = torch.empty_like(X1)
-    hf.sigma_device(X1, first1, order=1)
-    ref1, first1 = ref1.cpu().numpy(), first1.cpu().numpy()
-    hf.close()
-    del Xf, outf
-    torch.cuda.empty_cache()
-    err = np.abs(red1 - ref1).max()
-    rel_total = float(err / np.abs(ref1).max())
-    rel_second = float(err / np.abs(ref1 - first1).max())
-    fp64_tflops = stf["product_flops"] / elf / 1e12
-    fp64_hhat = stf["hhat_flops"] / stf["hhat_seconds"] / 1e12 if stf["hhat_seconds"] > 0 else 0.0
-    log(f"fp64: {fp64_tflops:.1f} TF/s, amplitude GEMM {fp64_hhat:.1f} TF/s; reduced vs FP64 rel err "
-        f"{rel_total:.2e} (second-order part {rel_second:.2e})")
+    rel_total = rel_second = fp64_tflops = fp64_hhat = None
+    fsteps = 0
+    if not args.no_fp64:
+        # FP64 beside it: same step, 4 trial vectors (memory), and the FP64 pass on the reduced one's vectors
+        hf, setup64 = make_handle(P.PP_FP64)
+        log(f"fp64 handle set up in {setup64:.1f} s")
+        Xf = vectors(PRODUCT_M_FP64)
+        outf = torch.empty_like(Xf)
+        fsteps = max(1, min(2, args.steps))
+        elf, stf = timed_parts(hf, Xf, outf, False, 1 if args.warmup else 0, fsteps)
+        ref1 = torch.empty_like(X1)
+        hf.sigma_device(X1, ref1)
+        first1 = torch.empty_like(X1)
+        hf.sigma_device(X1, first1, order=1)
+        ref1, first1 = ref1.cpu().numpy(), first1.cpu().numpy()
+        hf.close()
+        del Xf, outf
+        torch.cuda.empty_cache()
+        err = np.abs(red1 - ref1).max()
+        rel_total = float(err / np.abs(ref1).max())
+        rel_second = float(err / np.abs(ref1 - first1).max())
+        fp64_tflops = stf["product_flops"] / elf / 1e12
+        fp64_hhat = stf["hhat_flops"] / stf["hhat_seconds"] / 1e12 if stf["hhat_seconds"] > 0 else 0.0
+        log(f"fp64: {fp64_tflops:.1f} TF/s, amplitude GEMM {fp64_hhat:.1f} TF/s; reduced vs FP64 rel err "
+            f"{rel_total:.2e} (second-order part {rel_second:.2e})")
 
     line = {
         "metric": "window solves/sec + sigma-build TFLOP/s at 1e-6 Ha; p50/p99 solve latency",
@@ -611,7 +618,7 @@ def product_main(args):
         "fp64_amplitude_gemm_tflops": fp64_hhat,
         "fp64_vectors": 2 * PRODUCT_M_FP64,
         "fp64_steps": fsteps,
-        "reduced_over_fp64": value / fp64_tflops if fp64_tflops > 0 else None,
+        "reduced_over_fp64": value / fp64_tflops if fp64_tflops else None,
         "roofline": {"bound": "mfma",
                      "kernel": "gemm_sbf16_kernel<256,256,4,2,2,1> (H = tau G of one amplitude strip: split-BF16, "
                                "three BF16 MFMAs per FP32-equivalent product), priced against the BF16 peak / 3",

@@ -98,7 +98,9 @@ void gemm_f64_hhat(const GemmDesc& d, double alpha, const double* A, const doubl
 // aligned, zero past K in a row's last chunk; no batch or outer reduction; C index splits
 // allowed; d.tile = 128 or 256 fixes the tile shape (results do not depend on it).  Used
 // for the amplitude contraction (and the amplitude strips' integrals) in PP_SPLIT_BF16 mode.
-void gemm_sbf16(const GemmDesc& d, float alpha, const float* A, const float* B, float beta, float* C, hipStream_t s);
+// amplitude = true launches the same kernel under the amplitude contraction's own symbol.
+void gemm_sbf16(const GemmDesc& d, float alpha, const float* A, const float* B, float beta, float* C, hipStream_t s,
+                bool amplitude = false);
 // Splits n FP32 values in place (n a multiple of 8, x 16-byte aligned): each chunk of 8
 // values becomes their 8 bf16 hi parts, hi = bf16(x) rounded to nearest even, followed
 // by their 8 lo parts, lo = bf16(x - hi).
@@ -113,7 +115,8 @@ int gemm_auto_splitk(const GemmDesc& d, size_t ws_bytes, bool fp32);
 
 // Algorithmic flop count of a GemmDesc (2 per multiply-add).
 // One GEMM of a set issued together (C = alpha op(A) op(B) + beta C); tag 1 selects the
-// kernel symbol of the amplitude contraction.  ws is the member's split-K workspace
+// kernel symbol of the amplitude contraction, tag 2 the split-BF16 kernel (operands in
+// the split layout) and tag 3 that kernel under the amplitude contraction's symbol.  ws is the member's split-K workspace
 // for when it is launched on its own.
 template <typename T>
 struct GemmCall {

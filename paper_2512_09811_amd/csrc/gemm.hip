@@ -801,9 +801,9 @@ void group_dispatch(bool big, bool ak, bool bk, const GemmCall<T>* const* calls,
 
 template <typename T>
 void single_dispatch(const GemmCall<T>& c, hipStream_t s) {
-  if (c.tag == 2) {
+  if (c.tag >= 2) {
     if constexpr (std::is_same<T, float>::value)
-      gemm_sbf16(c.d, c.alpha, c.A, c.B, c.beta, c.C, s);
+      gemm_sbf16(c.d, c.alpha, c.A, c.B, c.beta, c.C, s, c.tag == 3);
     else
       throw InvalidArg("split-BF16 products take FP32 operands");
     return;
@@ -832,7 +832,7 @@ int gemm_group_impl(const std::vector<GemmCall<T>>& calls, hipStream_t s) {
     const GemmDesc& d = c.d;
     if (d.M <= 0 || d.N <= 0 || d.nb1 <= 0 || d.nb2 <= 0) continue;
     if (d.K <= 0 || d.KB <= 0) throw InvalidArg("gemm: empty reduction");
-    if (d.splitk > 1 || c.tag == 2) {
+    if (d.splitk > 1 || c.tag >= 2) {
       // fixed reduction splits need the split-K launch; split-BF16 has its own kernel
       single_dispatch(c, s);
       continue;
@@ -898,8 +898,9 @@ __device__ __forceinline__ int row32(int lane, int r) { return 8 * (r >> 2) + 4 
 
 // WM x WN waves (64 WM WN threads), each owning a (BM / WM) x (BN / WN) block of the tile;
 // ST LDS buffers, the loads of tile kt + ST - 1 issued while tile kt is multiplied; OCC
-// workgroups per CU (register budget).
-template <int BM, int BN, int WM, int WN, int ST, int OCC>
+// workgroups per CU (register budget).  TAG only distinguishes kernel symbols (1: the
+// amplitude contraction, so that profiles can attribute its time); the code is identical.
+template <int BM, int BN, int WM, int WN, int ST, int OCC, int TAG = 0>
 __global__ __launch_bounds__(64 * WM * WN, OCC) void gemm_sbf16_kernel(
     GemmDesc d, float alpha, const float* __restrict__ A, const float* __restrict__ B, float beta,
     float* __restrict__ C) {
@@ -1114,7 +1115,8 @@ int gemm_auto_splitk(const GemmDesc& d, size_t ws_bytes, bool fp32) {
   return auto_splitk(ntiles * nbatch, total, per, ws_bytes);
 }
 
-void gemm_sbf16(const GemmDesc& d, float alpha, const float* A, const float* B, float beta, float* C, hipStream_t s) {
+void gemm_sbf16(const GemmDesc& d, float alpha, const float* A, const float* B, float beta, float* C, hipStream_t s,
+                bool amplitude) {
   if (d.M <= 0 || d.N <= 0) return;
   if (d.K <= 0) throw InvalidArg("gemm: empty reduction");
   if (d.transA != 0 || d.transB == 0 || d.KB != 1 || d.nb1 != 1 || d.nb2 != 1)
@@ -1133,10 +1135,16 @@ void gemm_sbf16(const GemmDesc& d, float alpha, const float* A, const float* B, 
     const double r256 = (double)((t256 + kCUs - 1) / kCUs), r128 = (double)((t128 + 2 * kCUs - 1) / (2 * kCUs));
     if (d.tile == 256 || (d.tile != 128 && r256 * 2.0 / 1.05 < r128)) {
       const long wgs = checked_workgroups<256, 256, kSbBK>(d);
-      gemm_sbf16_kernel<256, 256, 4, 2, 2, 1><<<dim3((unsigned)wgs), 512, 0, s>>>(d, alpha, A, B, beta, C);
+      if (amplitude)
+        gemm_sbf16_kernel<256, 256, 4, 2, 2, 1, 1><<<dim3((unsigned)wgs), 512, 0, s>>>(d, alpha, A, B, beta, C);
+      else
+        gemm_sbf16_kernel<256, 256, 4, 2, 2, 1><<<dim3((unsigned)wgs), 512, 0, s>>>(d, alpha, A, B, beta, C);
     } else {
       const long wgs = checked_workgroups<128, 128, kSbBK>(d);
-      gemm_sbf16_kernel<128, 128, 2, 2, 2, 2><<<dim3((unsigned)wgs), kThreads, 0, s>>>(d, alpha, A, B, beta, C);
+      if (amplitude)
+        gemm_sbf16_kernel<128, 128, 2, 2, 2, 2, 1><<<dim3((unsigned)wgs), kThreads, 0, s>>>(d, alpha, A, B, beta, C);
+      else
+        gemm_sbf16_kernel<128, 128, 2, 2, 2, 2><<<dim3((unsigned)wgs), kThreads, 0, s>>>(d, alpha, A, B, beta, C);
     }
   } else {
     const long wgs = checked_workgroups<64, 64, kSbBK>(d);

@@ -391,10 +391,10 @@ void gemm_t<float>(const GemmDesc& d, float a, const float* A, const float* B, f
 }
 // Split-BF16 amplitude contraction (FP32 operands only).
 inline void gemm_sbf16_t(const GemmDesc& d, float a, const float* A, const float* B, float b, float* C,
-                         hipStream_t s) {
-  gemm_sbf16(d, a, A, B, b, C, s);
+                         hipStream_t s, bool amplitude) {
+  gemm_sbf16(d, a, A, B, b, C, s, amplitude);
 }
-inline void gemm_sbf16_t(const GemmDesc&, double, const double*, const double*, double, double*, hipStream_t) {
+inline void gemm_sbf16_t(const GemmDesc&, double, const double*, const double*, double, double*, hipStream_t, bool) {
   throw InvalidArg("split-BF16 products take FP32 operands");
 }
 
@@ -460,8 +460,8 @@ struct Emit {
   std::vector<Step>* tape = nullptr;
   void gemm(const GemmDesc& d, T a, const T* A, const T* B, T b, T* C, Workspace ws, int tag = 0) {
     if (!tape) {
-      if (tag == 2)
-        gemm_sbf16_t(d, a, A, B, b, C, s);
+      if (tag >= 2)
+        gemm_sbf16_t(d, a, A, B, b, C, s, tag == 3);
       else if (tag == 1)
         gemm_hhat_t<T>(d, a, A, B, b, C, s, ws);
       else
@@ -646,7 +646,7 @@ void contract(Context& c, const Ops<T>& t, Emit<T>& e, int order, int k, const T
     }
   };
   // the amplitude contraction: its own kernel symbol, or split-BF16 products in that mode
-  const int hhat_tag = (sizeof(T) == sizeof(float) && c.split_bf16) ? 2 : 1;
+  const int hhat_tag = (sizeof(T) == sizeof(float) && c.split_bf16) ? 3 : 1;
   double hflops = 0.0;
   if (t.tau) {
     // stored amplitudes: the whole contraction in one GEMM, with the prologue
