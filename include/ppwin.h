@@ -186,6 +186,20 @@ pp_status pp_sigma_part(pp_handle* h, int32_t order, int32_t m, const double* X,
 /* Waits until every product enqueued on the handle with PP_ASYNC is done. */
 pp_status pp_sync(pp_handle* h);
 
+/* pp_sigma for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same product,
+ * same kernels and result, on device pointers only (PP_DEVICE_PTRS required), with the
+ * staging of the trial and product vectors in a fixed scratch array of the library
+ * (64 MiB per GPU, held until the process ends) and no timing events (the handle's
+ * stats do not count these products).  It calls no allocating routine: the handle's
+ * product workspace must already hold 2m vectors at the requested precision (an earlier
+ * pp_sigma or window solve with at least m vectors on the handle grows it).  Every call
+ * on one GPU shares that GPU's scratch array, so calls that overlap on one GPU (other
+ * threads, other handles, PP_ASYNC calls not yet finished) race; with PP_ASYNC the
+ * scratch stays in use until the work is done.  Errors: PP_EINVAL for host pointers,
+ * 4 * 2m * N > 8 Mi doubles, or a workspace not yet reserved; otherwise as pp_sigma. */
+pp_status pp_sigma_static(pp_handle* h, int32_t order, int32_t m, const double* X, double* out, uint32_t flags);
+
 /* Roots of M z = omega Sigma z nearest omega0 on the positive branch, at the
  * handle's setup order: energies[n_roots] ascending (Ha); vectors
  * [n_roots][2][n_occ][n_vir] with X^T S X - Y^T S Y = 1 (nullable); osc

@@ -118,6 +118,8 @@ def lib() -> C.CDLL:
         L.pp_mp2_energy.restype = dbl
         L.pp_device_bytes.argtypes = [vp]
         L.pp_device_bytes.restype = u64
+        L.pp_sigma_static.argtypes = [vp, i32, i32, vp, vp, u32]
+        L.pp_sigma_static.restype = C.c_int
         L.pp_sigma_part.argtypes = [vp, i32, i32, vp, vp, u32, i32, i32]
         L.pp_sigma_part.restype = C.c_int
         L.pp_sync.argtypes = [vp]
@@ -265,6 +267,15 @@ class Handle:
         flags = (PP_DEVICE_PTRS | (PP_APPLY_METRIC if metric else 0) | (PP_ASYNC if async_ else 0)
                  | (PP_REDUCED if reduced else 0))
         st = lib().pp_sigma(self.h, self.order if order is None else order, m, X.data_ptr(), out.data_ptr(), flags)
+        _check(st, self.h)
+
+    def sigma_static(self, X, out, order: Optional[int] = None, metric: bool = False, reduced: bool = False):
+        """pp_sigma_static on torch device tensors [m][2][N]: the product with no allocation
+        (staging in the library's fixed scratch array)."""
+        m = X.shape[0]
+        flags = PP_DEVICE_PTRS | (PP_APPLY_METRIC if metric else 0) | (PP_REDUCED if reduced else 0)
+        st = lib().pp_sigma_static(self.h, self.order if order is None else order, m, X.data_ptr(),
+                                   out.data_ptr(), flags)
         _check(st, self.h)
 
     def sigma_part(self, X, out, part: int, n_parts: int, order: Optional[int] = None, metric: bool = False,

@@ -2,6 +2,7 @@
 // marshalling.  No exception leaves this file.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -39,6 +40,30 @@ namespace {
 
 thread_local std::string g_setup_error;
 using ppw::guarded;
+
+// Staging of pp_sigma_static: a fixed device array, one copy per GPU, shared by every
+// call on that GPU (calls that overlap on one GPU race).  Host code never passes the
+// array's name to a kernel: it uses the device address taken once per device with
+// hipGetSymbolAddress.
+constexpr size_t kScratchDoubles = (size_t)8 << 20;  // 64 MiB
+__device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this GPU's scratch array (the device must be current).
+double* scratch_on(int device) {
+  if (device < 0 || device >= kMaxDevices) throw ppw::InvalidArg("device ordinal out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    PPW_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw ppw::DeviceError("hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_ptr[device] = static_cast<double*>(p);
+  }
+  return g_scratch_ptr[device];
+}
 
 }  // namespace
 
@@ -285,6 +310,50 @@ pp_status pp_sigma_part(pp_handle* h, int32_t order, int32_t m, const double* X,
       // the staging may still be read by enqueued work: keep it until that is settled
       if (!async) drop_parts(h);
     }
+  });
+}
+
+pp_status pp_sigma_static(pp_handle* h, int32_t order, int32_t m, const double* X, double* out, uint32_t flags) {
+  if (!h || !h->ctx) return PP_EINVAL;
+  return guarded(&h->err, [&] {
+    ppw::Context& c = *h->ctx;
+    if (m < 0) throw ppw::InvalidArg("m must be >= 0");
+    if (order < 0 || order > c.order) throw ppw::InvalidArg("order exceeds the setup order");
+    if (m == 0) return;
+    if (!X || !out) throw ppw::InvalidArg("NULL vector pointer");
+    if (!(flags & PP_DEVICE_PTRS)) throw ppw::InvalidArg("pp_sigma_static takes device pointers (PP_DEVICE_PTRS)");
+    const int prec = product_precision(h, flags);
+    const long N = c.N;
+    const int k = 2 * m;
+    const size_t per = (size_t)k * N;
+    if (4 * per > kScratchDoubles)
+      throw ppw::InvalidArg("pp_sigma_static: 4 * 2m * N = " + std::to_string(4 * per) +
+                            " doubles of staging exceed its fixed scratch of " + std::to_string(kScratchDoubles));
+    if (!ppw::sigma_workspace_ready(c, order, k, prec))
+      throw ppw::InvalidArg("pp_sigma_static: the handle's product workspace does not hold 2m vectors at this "
+                            "precision yet (one pp_sigma call with at least m vectors reserves it)");
+    PPW_HIP(hipSetDevice(c.device));
+    settle(h);
+    double* V = scratch_on(c.device);
+    double* AV = V + per;
+    double* BV = AV + per;
+    double* SV = BV + per;
+    PPW_HIP(hipMemcpy2DAsync(V, N * sizeof(double), X, 2 * N * sizeof(double), N * sizeof(double), m,
+                             hipMemcpyDeviceToDevice, c.stream));
+    PPW_HIP(hipMemcpy2DAsync(V + (size_t)m * N, N * sizeof(double), X + N, 2 * N * sizeof(double),
+                             N * sizeof(double), m, hipMemcpyDeviceToDevice, c.stream));
+    struct Quiet {
+      ppw::Context& c;
+      ~Quiet() { c.no_events = false; }
+    } quiet{c};
+    c.no_events = true;
+    ppw::sigma_pass(c, order, k, prec, V, AV, BV, SV, ppw::PassRange{});
+    ppw::combine_pairs(N, m, AV, BV, SV, (flags & PP_APPLY_METRIC) != 0, out, c.stream);
+    if (flags & PP_ASYNC) {
+      h->pending = true;
+      return;
+    }
+    PPW_HIP(hipStreamSynchronize(c.stream));
   });
 }
 

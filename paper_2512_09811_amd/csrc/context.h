@@ -204,6 +204,7 @@ struct Context {
   SigmaStats stats;
   EventLog events;
   long pass_serial = 0;  // product passes started on this context (a part sequence checks it)
+  bool no_events = false;  // products record no timing events (and create none)
   std::string last_error;
 
   // folds pending event timings into stats (synchronizes on them)
@@ -269,6 +270,10 @@ struct Footprint {
 };
 Footprint context_footprint(int o, int v, int naux, int order, bool dip, bool store, int strip_rows, bool want_f32,
                             int k, bool split = false);
+
+// Whether the product workspace already holds k vectors at that order and precision,
+// so that a pass allocates nothing.
+bool sigma_workspace_ready(const Context& c, int order, int k, int prec);
 
 // Grows the product workspace to k vectors ahead of time (no allocation in the loop).
 void sigma_reserve(Context& c, int k, int precision);

@@ -52,6 +52,8 @@ void build_ring_operand(const double* Bov, const double* Lam, int o, int v, int 
 // y = alpha*x + beta*y (n elements), and conversions.
 void axpby(long n, double alpha, const double* x, double beta, double* y, hipStream_t s);
 void to_f32(long n, const double* x, float* y, hipStream_t s);
+// y[0..n) = 0 (a kernel, so that it can sit in a captured graph).
+void fill_zero(long n, double* y, hipStream_t s);
 // y[r][c] = x[r][c] (c < cols) and 0 (cols <= c < ldy) as FP32, for rows r < rows.
 void to_f32_rows(long rows, long cols, const double* x, long ldx, float* y, long ldy, hipStream_t s);
 // y[c][r] = x[r][c] (r < rows) and 0 (rows <= r < ldy) as FP32, for columns c < cols:

@@ -240,6 +240,10 @@ __global__ void dos_kernel(int o, int v, const double* __restrict__ eo, const do
   }
 }
 
+__global__ void fill_zero_kernel(long n, double* __restrict__ y) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) y[i] = 0.0;
+}
+
 __global__ void to_f32_rows_kernel(long rows, long cols, const double* __restrict__ x, long ldx,
                                    float* __restrict__ y, long ldy) {
   const long n = rows * ldy;
@@ -379,6 +383,12 @@ void axpby(long n, double alpha, const double* x, double beta, double* y, hipStr
 
 void to_f32(long n, const double* x, float* y, hipStream_t s) {
   to_f32_kernel<<<grid_for(n), kBlock, 0, s>>>(n, x, y);
+  PPW_LAUNCH_CHECK();
+}
+
+void fill_zero(long n, double* y, hipStream_t s) {
+  if (n <= 0) return;
+  fill_zero_kernel<<<grid_for(n), kBlock, 0, s>>>(n, y);
   PPW_LAUNCH_CHECK();
 }
 

@@ -655,7 +655,7 @@ void contract(Context& c, const Ops<T>& t, Emit<T>& e, int order, int k, const T
     GemmDesc d = gd((int)N, (int)kX, (int)N, 0, t.ldtau, 1, t.ldG, X);
     d.cRn = X;
     d.cSn = N * X;
-    const int ev = e.tape ? -1 : c.events.start(s);
+    const int ev = (e.tape || c.no_events) ? -1 : c.events.start(s);
     e.gemm(d, one, t.tau, t.G, zero, t.H, c.ws, hhat_tag);
     if (ev >= 0) c.events.stop(ev, s, 1);
     hflops += gemm_flops(d);
@@ -688,7 +688,7 @@ void contract(Context& c, const Ops<T>& t, Emit<T>& e, int order, int k, const T
       GemmDesc d = gd(nb * v, (int)kX, (int)N, 0, t.ldst, 1, t.ldG, X);
       d.cRn = X;
       d.cSn = (long)nb * v * X;
-      const int ev = e.tape ? -1 : c.events.start(s);
+      const int ev = (e.tape || c.no_events) ? -1 : c.events.start(s);
       e.gemm(d, one, t.tau_w, t.G, zero, t.H, c.ws, hhat_tag);
       if (ev >= 0) c.events.stop(ev, s, 1);
       hflops += gemm_flops(d);
@@ -779,8 +779,8 @@ void emit_pass(Context& c, int order, int k, int prec, const double* V, double* 
     Emit<double> em;
     em.s = s;
     em.tape = tape;
-    const size_t bytes = sizeof(double) * (size_t)k * c.N;
-    em.call([=](hipStream_t st) { PPW_HIP(hipMemsetAsync(BV, 0, bytes, st)); });
+    const long n = (long)k * c.N;
+    em.call([=](hipStream_t st) { fill_zero(n, BV, st); });
   }
 }
 
@@ -846,10 +846,14 @@ void pass_on_stream(Context& c, int order, int k, int prec, const double* V, dou
     emit_pass(c, 0, k, prec, V, AV, BV, SV, s, nullptr, rg);
     return;
   }
-  if (c.events.pending() > 4096) c.resolve_stats();
-  const int ev_pass = c.events.start(s);
-  emit_pass(c, order, k, prec, V, AV, BV, SV, s, nullptr, rg);
-  c.events.stop(ev_pass, s, 0);
+  if (c.no_events) {
+    emit_pass(c, order, k, prec, V, AV, BV, SV, s, nullptr, rg);
+  } else {
+    if (c.events.pending() > 4096) c.resolve_stats();
+    const int ev_pass = c.events.start(s);
+    emit_pass(c, order, k, prec, V, AV, BV, SV, s, nullptr, rg);
+    c.events.stop(ev_pass, s, 0);
+  }
   const int r0 = std::max(rg.i0, 0), r1 = std::min(rg.i1 < 0 ? c.o : rg.i1, c.o);
   double pre, strips;
   pass_flops(c, order, k, prec, std::max(0, r1 - r0), &pre, &strips);
@@ -867,6 +871,12 @@ void sigma_core(Context& c, int order, int k, const double* V, double* AV, doubl
 
 void sigma_core_f32(Context& c, int order, int k, const double* V, double* AV, double* BV, double* SV) {
   pass_on_stream(c, order, k, 1, V, AV, BV, SV, PassRange{});
+}
+
+bool sigma_workspace_ready(const Context& c, int order, int k, int prec) {
+  if (order < 1) return true;
+  if (k > c.kcap_asm) return false;
+  return prec == 1 ? k <= c.kcap32 : k <= c.kcap;
 }
 
 void sigma_pass(Context& c, int order, int k, int prec, const double* V, double* AV, double* BV, double* SV,
