@@ -262,10 +262,28 @@ pp_status pp_exciton_dos(pp_handle* h, int32_t n_bins, const double* edges, doub
  * the roots' oscillator strengths broadened in frequency): for each grid point w_g,
  *     out[g] = sum_k osc[k] * (eta/pi) / ((w_g - energies[k])^2 + eta^2)
  * (a Lorentzian of half width eta per root; its integral over w is osc[k]).  Host
- * pointers: energies[n], osc[n], omega[n_omega], out[n_omega].  Host-only (no device
- * work); PP_EINVAL for n < 0, n_omega < 0, eta <= 0 or NULL arrays with positive sizes. */
+ * pointers: energies[n], osc[n], omega[n_omega], out[n_omega]; computed on the current
+ * HIP device (the arrays are copied there and back).  PP_EINVAL for n < 0, n_omega < 0,
+ * eta <= 0, energies not positive, non-finite values or NULL arrays with positive sizes;
+ * PP_EDEVICE on a HIP error. */
 pp_status pp_spectrum(int32_t n, const double* energies, const double* osc, int32_t n_omega, const double* omega,
                       double eta, double* out);
+
+/* The isotropic dipole polarization propagator (Theory section: the propagator in its
+ * non-diagonal representation, eq. pp_adc, Pi = F^T (w Sigma - M)^-1 F for the pencil of
+ * the generalized eigenvalue equation) assembled from window roots in its spectral form:
+ *     Pi(w) = sum_k osc[k] / (2 energies[k]) [1 / (w - energies[k]) - 1 / (w + energies[k])]
+ * at w = omega[g] + i eta, i.e. (1/3) sum_x F_x^T (w Sigma - M)^-1 F_x with
+ * F_x = sqrt(2) [mu_x; mu_x] restricted to the given roots (each positive root with its
+ * partner -energies[k] on the negative branch; osc as the window solves return them, so
+ * F = S mu with opt->correlated_f).  Given every root, it equals the resolvent form;
+ * -Im Pi is the absorption-like spectrum and -Pi(0) the static polarizability.  Host
+ * pointers: energies[n] (> 0, Ha), osc[n], omega[n_omega] (Ha), re and im [n_omega];
+ * eta >= 0 (Ha; 0 gives the real axis, infinite at a root).  Computed on the current HIP
+ * device.  PP_EINVAL for negative sizes, energies not positive, eta < 0, non-finite
+ * values or NULL arrays with positive sizes; PP_EDEVICE on a HIP error. */
+pp_status pp_response(int32_t n, const double* energies, const double* osc, int32_t n_omega, const double* omega,
+                      double eta, double* re, double* im);
 
 /* ------------------------------------------------------------------------
  * Serving: a persistent request loop for window solves of differing systems.

@@ -41,6 +41,13 @@ pp_status ppint_gemm_cmap(int32_t fp32, int32_t M, int32_t N, int32_t K, int32_t
                           int64_t ldb, int64_t ldc, int32_t cRm, int64_t cSm, int32_t cRn, int64_t cSn, double alpha,
                           const void* A, const void* B, double beta, void* C, uint64_t ws_bytes);
 
+/* Failure injection from the host: from now on, the after_calls-th HIP runtime call the
+ * library checks reports the HIP error 'code' in place of its own return value (the
+ * call itself runs as usual), so the entry point that made it fails with PP_EDEVICE and
+ * the message of that error; the hook then disarms.  after_calls = 0 disarms it.  No
+ * kernel or device state is touched.  PP_EINVAL for after_calls < 0 or a zero code. */
+pp_status ppint_inject_hip_error(int32_t after_calls, int32_t code);
+
 /* The split layout of the split-BF16 products, in place on n float values (device, n a
  * multiple of 8, 16-byte aligned): every chunk of 8 values becomes 8 bf16 hi parts
  * hi = bf16(x) (round to nearest even) followed by 8 bf16 lo parts lo = bf16(x - hi).

@@ -116,3 +116,35 @@ def exciton_dos(eps_o, eps_v, dip, edges):
         counts[b] = np.count_nonzero(inside)
         weights[b] = mu2[inside].sum()
     return counts, weights
+
+
+def response_resolvent(A, B, S, dip, omega, eta, F=None):
+    """The isotropic polarization propagator of the dipole operator from its non-diagonal
+    representation (Theory section, eq. pp_adc): Pi(w) = (1/3) sum_x F_x^T (w Sigma - M)^-1 F_x
+    at complex w = omega + i eta, with M = [[A, B], [B, A]], Sigma = diag(S, -S) (the pencil
+    of the generalized eigenvalue equation, whose metric the resolvent carries) and the
+    property vector F_x = sqrt(2) [mu_x; mu_x] of a singlet excitation (or F given as
+    [3][o*v], entering as [F_x; F_x]).  One dense complex solve per frequency, both branches
+    at once.  Returns a complex array over omega."""
+    N = A.shape[0]
+    M = np.block([[A, B], [B, A]]).astype(complex)
+    Sig = np.block([[S, np.zeros_like(S)], [np.zeros_like(S), -S]]).astype(complex)
+    mu = (dip.reshape(3, -1) if F is None else np.asarray(F).reshape(3, -1))
+    Fx = np.sqrt(2.0) * np.concatenate([mu, mu], axis=1).T.astype(complex)   # (2N, 3)
+    out = np.empty(len(np.atleast_1d(omega)), dtype=complex)
+    for n, w in enumerate(np.atleast_1d(omega)):
+        z = complex(w, eta)
+        sol = np.linalg.solve(z * Sig - M, Fx)
+        out[n] = np.sum(Fx * sol) / 3.0
+    assert N == mu.shape[1]
+    return out
+
+
+def response_from_roots(omega_k, f_k, omega, eta):
+    """The same propagator summed over the roots of the pencil (its spectral form):
+    Pi(w) = sum_k f_k / (2 omega_k) [1 / (w - omega_k) - 1 / (w + omega_k)], w = omega + i eta,
+    each positive root with its partner -omega_k on the negative branch."""
+    w = np.atleast_1d(omega)[:, None] + 1j * eta
+    wk = np.asarray(omega_k)[None, :]
+    c = (np.asarray(f_k) / (2.0 * np.asarray(omega_k)))[None, :]
+    return np.sum(c * (1.0 / (w - wk) - 1.0 / (w + wk)), axis=1)

@@ -136,6 +136,8 @@ def lib() -> C.CDLL:
         L.ppint_gemm_cmap.argtypes = [i32, i32, i32, i32, i32, i64, i32, i64, i64, i32, i64, i32, i64, dbl, vp, vp,
                                       dbl, vp, C.c_uint64]
         L.ppint_gemm_cmap.restype = C.c_int
+        L.ppint_inject_hip_error.argtypes = [i32, i32]
+        L.ppint_inject_hip_error.restype = C.c_int
         L.ppint_split_sbf16.argtypes = [i64, vp]
         L.ppint_split_sbf16.restype = C.c_int
         L.ppint_gemm_group.argtypes = [i32, i32, C.POINTER(ppint_gemm_member), C.POINTER(i32)]
@@ -152,6 +154,8 @@ def lib() -> C.CDLL:
         L.ppint_riesz_filter.restype = C.c_int
         L.pp_exciton_dos.argtypes = [vp, i32, vp, vp, vp]
         L.pp_exciton_dos.restype = C.c_int
+        L.pp_response.argtypes = [i32, vp, vp, i32, vp, dbl, vp, vp]
+        L.pp_response.restype = C.c_int
         L.pp_spectrum.argtypes = [i32, vp, vp, i32, vp, dbl, vp]
         L.pp_spectrum.restype = C.c_int
         L.pp_server_create.argtypes = [C.POINTER(pp_options), u64, i32, C.POINTER(vp)]
@@ -398,6 +402,11 @@ def gemm_cmap(A, B, C_, *, M, N, K, transA=0, lda, transB=0, ldb, ldc, cRm=0, cS
     _check(st)
 
 
+def inject_hip_error(after_calls: int, code: int = 0):
+    """Failure injection (test hook): the after_calls-th checked HIP call reports 'code'."""
+    _check(lib().ppint_inject_hip_error(int(after_calls), int(code)))
+
+
 def split_sbf16(x):
     """In-place split of a float32 device tensor into the split-BF16 chunk layout (test hook)."""
     _check(lib().ppint_split_sbf16(x.numel(), x.data_ptr()))
@@ -441,6 +450,18 @@ def spectrum(energies, osc, omega, eta: float) -> np.ndarray:
     _check(lib().pp_spectrum(len(e), e.ctypes.data, f.ctypes.data, len(w), w.ctypes.data, float(eta),
                              out.ctypes.data))
     return out
+
+
+def response(energies, osc, omega, eta: float) -> np.ndarray:
+    """The isotropic dipole propagator Pi(omega + i eta) assembled from roots (pp_response),
+    as a complex array over the grid omega."""
+    e, f, w = _f64(energies).ravel(), _f64(osc).ravel(), _f64(omega).ravel()
+    if e.shape != f.shape:
+        raise ValueError("energies and osc must have the same length")
+    re, im = np.empty_like(w), np.empty_like(w)
+    _check(lib().pp_response(len(e), e.ctypes.data, f.ctypes.data, len(w), w.ctypes.data, float(eta),
+                             re.ctypes.data, im.ctypes.data))
+    return re + 1j * im
 
 
 class Server:

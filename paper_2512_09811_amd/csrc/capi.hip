@@ -1,5 +1,6 @@
 // C ABI of the ppwin library: argument checks, error translation, host<->device
 // marshalling.  No exception leaves this file.
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -35,6 +36,19 @@ struct pp_handle {
     double* dout = nullptr;
   } parts;
 };
+
+namespace {
+std::atomic<long> g_inject_countdown{0};
+std::atomic<int> g_inject_code{0};
+}  // namespace
+
+namespace ppw {
+hipError_t injected_hip_error(hipError_t e) {
+  if (g_inject_countdown.load(std::memory_order_relaxed) > 0 && g_inject_countdown.fetch_sub(1) == 1)
+    return static_cast<hipError_t>(g_inject_code.load());
+  return e;
+}
+}  // namespace ppw
 
 namespace {
 
@@ -481,22 +495,63 @@ pp_status pp_exciton_dos(pp_handle* h, int32_t n_bins, const double* edges, doub
   });
 }
 
+namespace {
+// Roots and a frequency grid (host arrays) to the current device, response_on_grid there,
+// results back: Pi's real and imaginary parts and the broadened strengths (each nullable).
+void grid_sums(int32_t n, const double* energies, const double* osc, int32_t n_omega, const double* omega,
+               double eta, double* re, double* im, double* lor) {
+  if (n_omega == 0) return;
+  std::vector<double> host;  // e, f, omega
+  host.insert(host.end(), energies, energies + n);
+  host.insert(host.end(), osc, osc + n);
+  host.insert(host.end(), omega, omega + n_omega);
+  const size_t nin = host.size(), nout = (size_t)3 * n_omega;
+  double* d = nullptr;
+  PPW_HIP(hipMalloc(&d, sizeof(double) * (nin + nout)));
+  struct Free {
+    double* p;
+    ~Free() { (void)hipFree(p); }
+  } fr{d};
+  PPW_HIP(hipMemcpy(d, host.data(), sizeof(double) * nin, hipMemcpyHostToDevice));
+  double* out = d + nin;
+  ppw::response_on_grid(n, d, d + n, n_omega, d + 2 * n, eta, re ? out : nullptr, im ? out + n_omega : nullptr,
+                        lor ? out + 2 * n_omega : nullptr, nullptr);
+  PPW_HIP(hipDeviceSynchronize());
+  if (re) PPW_HIP(hipMemcpy(re, out, sizeof(double) * n_omega, hipMemcpyDeviceToHost));
+  if (im) PPW_HIP(hipMemcpy(im, out + n_omega, sizeof(double) * n_omega, hipMemcpyDeviceToHost));
+  if (lor) PPW_HIP(hipMemcpy(lor, out + 2 * n_omega, sizeof(double) * n_omega, hipMemcpyDeviceToHost));
+}
+
+void check_roots(int32_t n, const double* energies, const double* osc, int32_t n_omega, const double* omega) {
+  if (n < 0 || n_omega < 0) throw ppw::InvalidArg("negative size");
+  if ((n > 0 && (!energies || !osc)) || (n_omega > 0 && !omega)) throw ppw::InvalidArg("NULL array");
+  for (int k = 0; k < n; ++k)
+    if (!(energies[k] > 0.0) || !std::isfinite(energies[k]) || !std::isfinite(osc[k]))
+      throw ppw::InvalidArg("energies must be positive and finite, strengths finite");
+  for (int g = 0; g < n_omega; ++g)
+    if (!std::isfinite(omega[g])) throw ppw::InvalidArg("non-finite frequency");
+}
+}  // namespace
+
 pp_status pp_spectrum(int32_t n, const double* energies, const double* osc, int32_t n_omega, const double* omega,
                       double eta, double* out) {
   g_setup_error.clear();
   return guarded(&g_setup_error, [&] {
-    if (n < 0 || n_omega < 0) throw ppw::InvalidArg("negative size");
+    check_roots(n, energies, osc, n_omega, omega);
     if (!(eta > 0.0) || !std::isfinite(eta)) throw ppw::InvalidArg("eta must be positive");
-    if ((n > 0 && (!energies || !osc)) || (n_omega > 0 && (!omega || !out))) throw ppw::InvalidArg("NULL array");
-    const double c = eta / 3.14159265358979323846;
-    for (int g = 0; g < n_omega; ++g) {
-      double acc = 0.0;
-      for (int k = 0; k < n; ++k) {
-        const double d = omega[g] - energies[k];
-        acc += osc[k] * c / (d * d + eta * eta);
-      }
-      out[g] = acc;
-    }
+    if (n_omega > 0 && !out) throw ppw::InvalidArg("NULL array");
+    grid_sums(n, energies, osc, n_omega, omega, eta, nullptr, nullptr, out);
+  });
+}
+
+pp_status pp_response(int32_t n, const double* energies, const double* osc, int32_t n_omega, const double* omega,
+                      double eta, double* re, double* im) {
+  g_setup_error.clear();
+  return guarded(&g_setup_error, [&] {
+    check_roots(n, energies, osc, n_omega, omega);
+    if (!(eta >= 0.0) || !std::isfinite(eta)) throw ppw::InvalidArg("eta must be >= 0 and finite");
+    if (n_omega > 0 && (!re || !im)) throw ppw::InvalidArg("NULL array");
+    grid_sums(n, energies, osc, n_omega, omega, eta, re, im, nullptr);
   });
 }
 
@@ -558,6 +613,18 @@ void sbf16_from_f32(ppw::GemmDesc d, float alpha, const float* A, const float* B
   (void)hipFree(Bs);
 }
 }  // namespace
+
+pp_status ppint_inject_hip_error(int32_t after_calls, int32_t code) {
+  g_setup_error.clear();
+  if (after_calls < 0 || (after_calls > 0 && code == 0)) {
+    g_setup_error = "after_calls must be >= 0 and code nonzero";
+    return PP_EINVAL;
+  }
+  g_inject_countdown.store(0);
+  g_inject_code.store(code);
+  g_inject_countdown.store(after_calls);
+  return PP_OK;
+}
 
 pp_status ppint_split_sbf16(int64_t n, float* x) {
   g_setup_error.clear();

@@ -32,9 +32,13 @@ struct NotSupported : std::runtime_error {
   explicit NotSupported(const std::string& m) : std::runtime_error(m) {}
 };
 
+// Test hook (ppint_inject_hip_error): while armed, the n-th HIP call checked by PPW_HIP
+// reports an injected error code in place of its own return value (the call itself ran).
+hipError_t injected_hip_error(hipError_t e);
+
 #define PPW_HIP(call)                                                                    \
   do {                                                                                   \
-    hipError_t e_ = (call);                                                              \
+    hipError_t e_ = ::ppw::injected_hip_error(call);                                     \
     if (e_ != hipSuccess)                                                                \
       throw ::ppw::DeviceError(std::string(#call) + ": " + hipGetErrorString(e_));       \
   } while (0)

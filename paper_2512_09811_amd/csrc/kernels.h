@@ -66,6 +66,13 @@ void exciton_dos(int o, int v, const double* eo, const double* ev, const double*
 
 void to_f64(long n, const float* x, double* y, hipStream_t s);
 
+// Over a frequency grid omega[n_omega], from n roots (energies e_k > 0, strengths f_k):
+//   re + i im = sum_k f_k / (2 e_k) [1 / (w - e_k) - 1 / (w + e_k)],  w = omega + i eta
+// (each output nullable), and lor = sum_k f_k (eta / pi) / ((omega - e_k)^2 + eta^2).
+// Device pointers; one thread per grid point, roots summed in index order.
+void response_on_grid(int n, const double* e, const double* f, int n_omega, const double* omega, double eta,
+                      double* re, double* im, double* lor, hipStream_t s);
+
 // Column statistics of k column-vectors of length n stored [k][n] (row-major per vector):
 // out[c] = sum_r x[c][r] * y[c][r] (wavefront-level reductions, deterministic order).
 void column_dots(const double* x, const double* y, long n, int k, double* out, hipStream_t s);

@@ -240,6 +240,28 @@ __global__ void dos_kernel(int o, int v, const double* __restrict__ eo, const do
   }
 }
 
+__global__ void response_kernel(int n, const double* __restrict__ e, const double* __restrict__ f, int ng,
+                                const double* __restrict__ om, double eta, double* __restrict__ re,
+                                double* __restrict__ im, double* __restrict__ lor) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ng) return;
+  const double w = om[g];
+  double sr = 0.0, si = 0.0, sl = 0.0;
+  const double eta2 = eta * eta;
+  for (int k = 0; k < n; ++k) {
+    const double c = f[k] / (2.0 * e[k]);
+    const double dm = w - e[k], dp = w + e[k];
+    const double qm = 1.0 / (dm * dm + eta2), qp = 1.0 / (dp * dp + eta2);
+    // 1 / (d + i eta) = (d - i eta) / (d^2 + eta^2)
+    sr += c * (dm * qm - dp * qp);
+    si += c * (-eta * qm + eta * qp);
+    sl += f[k] * qm;
+  }
+  if (re) re[g] = sr;
+  if (im) im[g] = si;
+  if (lor) lor[g] = sl * eta * 0.31830988618379067154;  // eta / pi
+}
+
 __global__ void fill_zero_kernel(long n, double* __restrict__ y) {
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) y[i] = 0.0;
 }
@@ -383,6 +405,13 @@ void axpby(long n, double alpha, const double* x, double beta, double* y, hipStr
 
 void to_f32(long n, const double* x, float* y, hipStream_t s) {
   to_f32_kernel<<<grid_for(n), kBlock, 0, s>>>(n, x, y);
+  PPW_LAUNCH_CHECK();
+}
+
+void response_on_grid(int n, const double* e, const double* f, int n_omega, const double* omega, double eta,
+                      double* re, double* im, double* lor, hipStream_t s) {
+  if (n_omega <= 0) return;
+  response_kernel<<<(n_omega + kBlock - 1) / kBlock, kBlock, 0, s>>>(n, e, f, n_omega, omega, eta, re, im, lor);
   PPW_LAUNCH_CHECK();
 }
 

@@ -52,21 +52,18 @@ def test_host_only_helpers(lib):
         assert lib.pp_status_string(code)
 
 
-def test_spectrum_host_entry():
-    """pp_spectrum (host-only): each root contributes a unit-area Lorentzian times its
-    oscillator strength; the integral over a wide grid is the sum of strengths, an
-    isolated peak has height f/(pi eta), and bad arguments are rejected."""
+def test_spectrum_and_response_argument_checks():
+    """pp_spectrum and pp_response refuse bad arguments before any device work."""
     import numpy as np
     import paper_2512_09811_amd as P
-    e = np.array([0.5, 0.9, 0.905, 2.0])
-    f = np.array([0.1, 0.02, 0.3, 0.05])
-    eta = 2e-3
-    w = np.linspace(-50.0, 60.0, 2_000_001)
-    s = P.spectrum(e, f, w, eta)
-    integral = np.sum(0.5 * (s[1:] + s[:-1]) * np.diff(w))
-    tails = (f.sum() * 2 * eta / np.pi) * (1 / 50.0)  # the Lorentzian mass outside the grid, to first order
-    assert abs(integral - f.sum()) < tails
-    peak = P.spectrum(e, f, np.array([2.0]), eta)[0]
-    assert abs(peak - f[3] / (np.pi * eta)) < 1e-3 * peak
+    e = np.array([0.5, 0.9])
+    f = np.array([0.1, 0.02])
+    w = np.linspace(0.0, 1.0, 10)
     with pytest.raises(P.PPError, match="eta must be positive"):
-        P.spectrum(e, f, w[:10], 0.0)
+        P.spectrum(e, f, w, 0.0)
+    with pytest.raises(P.PPError, match="eta must be >= 0"):
+        P.response(e, f, w, -1e-3)
+    with pytest.raises(P.PPError, match="energies must be positive"):
+        P.response(np.array([0.5, -0.1]), f, w, 1e-3)
+    with pytest.raises(P.PPError, match="energies must be positive"):
+        P.spectrum(np.array([0.5, np.nan]), f, w, 1e-3)

@@ -332,3 +332,59 @@ def test_exciton_dos_matches_oracle(P):
     c_ref, m_ref = pencil.exciton_dos(sys.eps_o, sys.eps_v, sys.dip, edges)
     np.testing.assert_array_equal(counts, c_ref)
     np.testing.assert_allclose(mu2, m_ref, rtol=1e-12, atol=1e-15)
+
+
+def test_spectrum_broadening(P):
+    """pp_spectrum (on the device): each root contributes a unit-area Lorentzian times its
+    oscillator strength; the integral over a wide grid is the sum of strengths and an
+    isolated peak has height f/(pi eta)."""
+    e = np.array([0.5, 0.9, 0.905, 2.0])
+    f = np.array([0.1, 0.02, 0.3, 0.05])
+    eta = 2e-3
+    w = np.linspace(-50.0, 60.0, 2_000_001)
+    s = P.spectrum(e, f, w, eta)
+    integral = np.sum(0.5 * (s[1:] + s[:-1]) * np.diff(w))
+    tails = (f.sum() * 2 * eta / np.pi) * (1 / 50.0)  # the Lorentzian mass outside the grid, to first order
+    assert abs(integral - f.sum()) < tails
+    peak = P.spectrum(e, f, np.array([2.0]), eta)[0]
+    assert abs(peak - f[3] / (np.pi * eta)) < 1e-3 * peak
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_response_from_windows_matches_resolvent(P, order):
+    """The propagator Pi(omega + i eta) of the library (pp_response), assembled from the
+    roots of window solves that together cover the whole spectrum of the 8/24/64 system
+    (192 roots; windows of 16 roots at every 8th oracle root and the last, the union
+    deduplicated),
+    against the oracle's resolvent form F^T (w Sigma - M)^-1 F by dense complex solves on
+    a frequency grid, real and imaginary parts, to 1e-8 of the largest value; the union of
+    the windows is exactly the oracle's set of roots."""
+    sys_ = gen(1, 8, 24, 64)
+    A, B, S = dense.assemble(sys_, order)
+    w_all, _, _ = pencil.solve_all(A, B, S)
+    centers = list(w_all[0::8]) + [w_all[-1]]
+    got_e, got_f = [], []
+    with P.Handle.from_system(sys_, order=order) as h:
+        E, _, F, infos = h.window_solve_batch(centers, 16, vectors=False, osc=True)
+    for k in range(len(centers)):
+        assert np.all(infos[k]["converged"] == 1)
+        got_e.extend(E[k])
+        got_f.extend(F[k])
+    got_e, got_f = np.array(got_e), np.array(got_f)
+    order_ = np.argsort(got_e, kind="stable")
+    got_e, got_f = got_e[order_], got_f[order_]
+    keep = np.concatenate([[True], np.diff(got_e) > 1e-9])
+    got_e, got_f = got_e[keep], got_f[keep]
+    assert len(got_e) == len(w_all) == sys_.N
+    np.testing.assert_allclose(got_e, w_all, rtol=0, atol=1e-8)
+    grid = np.linspace(0.0, 3.5, 351)
+    for eta in (0.01, 0.05):
+        pi_lib = P.response(got_e, got_f, grid, eta)
+        pi_ref = pencil.response_resolvent(A, B, S, sys_.dip, grid, eta)
+        scale = np.abs(pi_ref).max()
+        np.testing.assert_allclose(pi_lib.real, pi_ref.real, rtol=0, atol=1e-8 * scale)
+        np.testing.assert_allclose(pi_lib.imag, pi_ref.imag, rtol=0, atol=1e-8 * scale)
+    # static limit (eta = 0, omega = 0): minus the static polarizability
+    p0 = P.response(got_e, got_f, np.array([0.0]), 0.0)[0]
+    ref0 = pencil.response_resolvent(A, B, S, sys_.dip, [0.0], 0.0)[0]
+    assert abs(p0.real - ref0.real) < 1e-8 * abs(ref0.real) and p0.imag == 0.0

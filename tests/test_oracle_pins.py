@@ -455,3 +455,34 @@ def test_select_window_ties_take_the_lower_root():
     # result is ascending in omega whatever the input order
     perm = np.array([5, 3, 0, 4, 1, 2])
     assert sorted(om[perm][pencil.select_window(om[perm], 0.5, 3)].tolist()) == [0.4, 0.45, 0.55]
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_response_resolvent_limits_and_poles(order):
+    """The propagator from the resolvent of the pencil (one complex solve per frequency)
+    against what fixes it independently of any eigen-decomposition: the static limit
+    Pi(0) = -(4/3) sum_x mu_x^T (A + B)^-1 mu_x, the high-frequency limit
+    w^2 Pi(w) -> (4/3) sum_x mu_x^T S^-1 (A - B) S^-1 mu_x (the strength sum rule), and the
+    pole residues -eta Im Pi(w_k + i eta) -> f_k / (2 w_k) at an isolated root; then the
+    spectral form over all roots equals it on a grid."""
+    sys_ = gen(8, 6, 20, 40, b_scale=0.4)
+    A, B, S = dense.assemble(sys_, order)
+    mu = sys_.dip.reshape(3, -1)
+    static = -(4.0 / 3.0) * sum(m @ np.linalg.solve(A + B, m) for m in mu)
+    p0 = pencil.response_resolvent(A, B, S, sys_.dip, [0.0], 0.0)[0]
+    assert abs(p0.imag) < 1e-14 and abs(p0.real - static) < 1e-11 * abs(static)
+    Si = np.linalg.inv(S)
+    trk = (4.0 / 3.0) * sum(m @ Si @ (A - B) @ Si @ m for m in mu)
+    big = 1e4
+    pinf = pencil.response_resolvent(A, B, S, sys_.dip, [big], 0.0)[0]
+    assert abs(big * big * pinf.real - trk) < 1e-6 * trk
+    w, X, Y = pencil.solve_all(A, B, S)
+    f = pencil.oscillator_strengths(w, X, Y, sys_.dip)
+    gaps = np.minimum(np.diff(w, prepend=-1.0), np.diff(w, append=10.0))
+    k = int(np.argmax(gaps * (f > 1e-3 * f.max())))        # an isolated root with some strength
+    eta = 1e-7
+    pk = pencil.response_resolvent(A, B, S, sys_.dip, [w[k]], eta)[0]
+    assert abs(-eta * pk.imag - f[k] / (2 * w[k])) < 1e-4 * f[k] / (2 * w[k])
+    grid = np.linspace(0.2, 3.2, 37)
+    np.testing.assert_allclose(pencil.response_from_roots(w, f, grid, 0.02),
+                               pencil.response_resolvent(A, B, S, sys_.dip, grid, 0.02), rtol=1e-9, atol=0)
