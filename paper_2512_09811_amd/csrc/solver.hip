@@ -1250,8 +1250,10 @@ void Solver::run(double* energies, double* vectors, double* osc, pp_solve_info* 
       // solve continues as in FP64 (every later product FP64, restart blocks FP64);
       // the returned vectors are accepted on residuals of FP64 products only.
       if (!refined && (all || worst <= switch_tol || stalled)) {
+        // thick restart onto the block (inner pairs first): only its X+Y and X-Y halves
+        // get FP64 products, and every later product is FP64
         refined_ = true;
-        remultiply_basis();
+        restart(blk);
         refined = true;
         knew = 0;
         best_worst = 1e300;

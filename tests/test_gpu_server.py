@@ -159,3 +159,41 @@ def test_server_riesz_requests(P):
         e_ref, f_ref = _oracle(s, w, nr)
         _check_vs(r["energies"], r["osc"], e_ref, f_ref)
         assert np.all(r["converged"] == 1) and r["status"] == P.PP_OK
+
+
+def _request_golden():
+    import json
+    import os
+    return json.load(open(os.path.join(os.path.dirname(__file__), "golden", "serve_o40_v160_x480.json")))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "sbf16"])
+def test_server_o40_request_alone_and_in_mix(P, prec):
+    """A request of the serving stream's shape at n_occ = 40 (n_vir 160, n_aux 480; its
+    roots stored from the oracle's exact pencil solution) served alone, then in a mix with
+    smaller requests whose products share its passes: the same roots and strengths both
+    times, to the FP64 bar also when the subspace is built from split-BF16 products."""
+    g = _request_golden()
+    big = gen(g["seed"], g["o"], g["v"], g["naux"])
+    e_ref, f_ref = np.array(g["energies"]), np.array(g["osc"])
+    pp = {"fp64": P.PP_FP64, "sbf16": P.PP_SPLIT_BF16}[prec]
+    print(f"[server o40] {prec}: alone", flush=True)
+    with P.Server(precision=pp) as srv:
+        r = srv.wait(srv.submit_system(big, g["omega0"], g["n_roots"]))
+    _check_vs(r["energies"], r["osc"], e_ref, f_ref)
+    assert np.all(r["converged"] == 1) and np.all(r["residual"] <= 1e-8)
+    print(f"[server o40] {prec}: in a mix", flush=True)
+    mix = _systems()[:3]
+    with P.Server(precision=pp, max_active=8) as srv:
+        ids = [srv.submit_system(s, w, nr) for s, w, nr in mix[:2]]
+        ib = srv.submit_system(big, g["omega0"], g["n_roots"])
+        ids.append(srv.submit_system(*mix[2]))
+        rb = srv.wait(ib)
+        rs = [srv.wait(i) for i in ids]
+        st = srv.stats()
+    assert st["completed"] == 4 and st["failed"] == 0 and st["peak_running"] >= 2
+    _check_vs(rb["energies"], rb["osc"], e_ref, f_ref)
+    np.testing.assert_allclose(rb["energies"], r["energies"], rtol=0, atol=1e-9)
+    for (s, w, nr), q in zip(mix[:2] + mix[2:], rs):
+        e1, f1 = _oracle(s, w, nr)
+        _check_vs(q["energies"], q["osc"], e1, f1)
