@@ -124,6 +124,13 @@ def parse():
     ap.add_argument("--riesz", action="store_true",
                     help="Riesz-projector windows against folded inverse-Krylov windows on the same small and "
                          "mid-size systems (its own JSON line)")
+    ap.add_argument("--large", default=None, metavar="WORKLOAD",
+                    help="window solves of a system drawn on the device (mp2_o200_v800_x3000 or "
+                         "mp2_o256_v1024_x4096, amplitudes rebuilt in strips) in each precision of "
+                         "--large-precisions, roots cross-checked between them (its own JSON line)")
+    ap.add_argument("--large-precisions", default="sbf16,fp64")
+    ap.add_argument("--large-roots", type=int, default=4)
+    ap.add_argument("--large-omega", type=float, default=0.3)
     return ap.parse_args()
 
 
@@ -199,6 +206,81 @@ def riesz_main(args):
     print(json.dumps(dict(metric="window solves/s, Riesz projector vs folded inverse Krylov", unit="solves/s",
                           dtype="f64", data="synthetic (seeded generator)", solver_tol=args.tol,
                           results=results)), flush=True)
+
+
+def large_main(args):
+    """Window solves at the sizes where no dense oracle fits (amplitudes rebuilt in strips
+    every pass): one window per precision on a system drawn on the device, each on its own
+    handle (setup untimed), the roots of the reduced-precision solve checked against the
+    FP64 solve's at 1e-6 Ha and 1e-5 relative f; solves/s, products and sigma-build
+    TFLOP/s per precision."""
+    import torch
+    import paper_2512_09811_amd as P
+    from synth.device_gen import gen_device
+    from synth.gen import CONFIGS
+
+    name = args.large
+    cfg = CONFIGS[name]
+    P.lib()
+    t = gen_device(cfg["seed"], cfg["o"], cfg["v"], cfg["naux"])
+    torch.cuda.synchronize()
+    w0, nr = args.large_omega, args.large_roots
+    runs = {}
+    for pn in args.large_precisions.split(","):
+        t0 = time.perf_counter()
+        with P.Handle(t["eps"], t["B_oo"], t["B_ov"], t["B_vv"], t["dip"], order=2, device_ptrs=True,
+                      precision=PRECISIONS[pn], store_amplitudes=0, tol=args.tol) as h:
+            setup = time.perf_counter() - t0
+            print(f"[large] {name} {pn}: setup {setup:.1f} s", file=sys.stderr, flush=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            e, _, f, info = h.window_solve(w0, nr, vectors=False, allow_unconverged=True)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            st = h.stats()
+        runs[pn] = dict(seconds=dt, solves_per_s=1.0 / dt, setup_seconds=setup, products=int(info["products"]),
+                        cycles=int(info["cycles"]), converged=int(np.sum(info["converged"])),
+                        max_residual=float(np.max(info["residual"])),
+                        sigma_tflops=st["product_flops"] / st["product_seconds"] / 1e12 if st["product_seconds"] else 0.0,
+                        amplitude_gemm_tflops=st["hhat_flops"] / st["hhat_seconds"] / 1e12 if st["hhat_seconds"] else 0.0,
+                        sigma_fraction_of_time=st["product_seconds"] / dt,
+                        energies=[float(x) for x in e], osc=[float(x) for x in f])
+        print(f"[large] {name} {pn}: {dt:.1f} s, {info['products']} products, residual {np.max(info['residual']):.1e}",
+              file=sys.stderr, flush=True)
+    names = list(runs)
+    check = {}
+    if "fp64" in runs:
+        ref = runs["fp64"]
+        ge, gf = np.array(ref["energies"]), np.array(ref["osc"])
+        for pn in names:
+            if pn == "fp64":
+                continue
+            e, f = np.array(runs[pn]["energies"]), np.array(runs[pn]["osc"])
+            big = gf >= 1e-4 * gf.max()
+            de = float(np.abs(e - ge).max())
+            df = float(np.max(np.abs(f[big] - gf[big]) / gf[big]))
+            check[pn] = dict(max_abs_dE_ha=de, max_rel_df=df, within_1e6_ha_1e5_f=bool(de <= 1e-6 and df <= 1e-5))
+    first = runs[names[0]]
+    line = {
+        "metric": "window solves/sec + sigma-build TFLOP/s at 1e-6 Ha; p50/p99 solve latency",
+        "value": first["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": 1e3 * first["seconds"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPES[names[0]],
+        "data": "synthetic (seeded device generator; PbS/CdS orbitals and integrals are not available)",
+        "config": {"workload": f"{name}: second-order window solve, n_occ={cfg['o']}, n_vir={cfg['v']}, "
+                               f"n_aux={cfg['naux']}, 1 window at {w0} Ha x {nr} roots, amplitudes rebuilt in strips",
+                   "solver_tol": args.tol, "precisions": names, "parallelism": "single GPU"},
+        "runs": runs,
+        "reduced_vs_fp64": check,
+    }
+    print(json.dumps(line), flush=True)
 
 
 def serve_main(args):
@@ -663,6 +745,9 @@ def main():
         return
     if args.serve:
         serve_main(args)
+        return
+    if args.large:
+        large_main(args)
         return
     if args.workload != PRODUCT_WORKLOAD:
         line = windows_run(args, args.workload, args.precision or "fp64", args.steps, args.warmup,

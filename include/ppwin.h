@@ -125,6 +125,11 @@ typedef struct {
                                first cycle stop (default 1e-4); later cycles stop at a tenth of
                                the window's worst residual, down to tol / 10 */
   int32_t contour_maxit;    /* PP_RIESZ: iteration cap of each shifted solve (default 500) */
+  int32_t pass_vectors;     /* window solves: most particle-hole vectors per product pass (0,
+                               the default: as many as the windows request at once, fewer when
+                               their product workspaces would not fit the budget); a larger
+                               request runs as several passes of equal size, each of which
+                               rebuilds the amplitude strips when they are not stored */
 } pp_options;
 
 #define PP_MAX_ROOTS 64

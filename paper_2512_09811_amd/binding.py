@@ -45,7 +45,7 @@ class pp_options(C.Structure):
                 ("hbm_budget", C.c_uint64), ("device", C.c_int32), ("stream", C.c_void_p),
                 ("seed", C.c_uint64), ("tda", C.c_int32), ("correlated_f", C.c_int32),
                 ("method", C.c_int32), ("contour_nodes", C.c_int32), ("contour_tol", C.c_double),
-                ("contour_maxit", C.c_int32)]
+                ("contour_maxit", C.c_int32), ("pass_vectors", C.c_int32)]
 
 
 class pp_solve_info(C.Structure):

@@ -70,6 +70,7 @@ inline void check_options(const pp_options& opt) {
   if (opt.max_basis > 512) throw InvalidArg("max_basis must be <= 512");
   if (!(opt.tol > 0)) throw InvalidArg("tol must be positive");
   if (opt.method != PP_FOLDED && opt.method != PP_RIESZ) throw InvalidArg("unknown method");
+  if (opt.pass_vectors < 0) throw InvalidArg("pass_vectors must be >= 0");
   if (opt.method == PP_RIESZ) {
     if (opt.contour_nodes < 1 || opt.contour_nodes > 32) throw InvalidArg("contour_nodes must be in 1..32");
     if (!(opt.contour_tol > 0 && opt.contour_tol < 1)) throw InvalidArg("contour_tol must be in (0, 1)");
@@ -92,6 +93,7 @@ inline SolveOptions solve_options(const pp_options& o) {
   so.contour_nodes = o.contour_nodes;
   so.contour_tol = o.contour_tol;
   so.contour_maxit = o.contour_maxit;
+  so.pass_vectors = o.pass_vectors;
   return so;
 }
 

@@ -130,6 +130,7 @@ void pp_default_options(pp_options* opt) {
   opt->contour_nodes = 6;
   opt->contour_tol = 1e-4;
   opt->contour_maxit = 500;
+  opt->pass_vectors = 0;
 }
 
 pp_status pp_setup(const pp_system* sys, const pp_options* opt_in, pp_handle** out) {

@@ -277,6 +277,8 @@ bool sigma_workspace_ready(const Context& c, int order, int k, int prec);
 
 // Grows the product workspace to k vectors ahead of time (no allocation in the loop).
 void sigma_reserve(Context& c, int k, int precision);
+// Device bytes that sigma_reserve(c, k, precision) would add to the context's arena.
+size_t sigma_reserve_bytes(const Context& c, int k, int precision);
 
 // Algorithmic flops of one product pass over k vectors at the given order, with the
 // contractions of precision prec (0 FP64, 1 reduced); amplitudes that precision does not

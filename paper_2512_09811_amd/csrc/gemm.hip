@@ -877,7 +877,8 @@ int gemm_group_impl(const std::vector<GemmCall<T>>& calls, hipStream_t s) {
 // values 8c .. 8c+7 and then their 8 lo parts.  A value still occupies 4 bytes, so rows
 // keep their FP32 strides (a multiple of 8 values) and an FP32 array is split in place.
 //
-// Kernel: 256 threads as 2 x 2 wave64s, BM x BN tiles; a k tile is 32 values = 4 chunks
+// Kernel: WM x WN wave64s on BM x BN tiles (4 x 2 on 256 x 256 at one workgroup per CU,
+// 2 x 2 on 128 x 128 or 64 x 64 at two), ST LDS stages; a k tile is 32 values = 4 chunks
 // = 128 B per row, loaded straight into LDS (global_load_lds_dwordx4) in the swizzled
 // slot layout of the FP64 kernel (16-byte slot s of row r at 8r + (s ^ ((r >> 1) & 7)),
 // logical slot 2c holding chunk c's hi parts and 2c + 1 its lo parts), so a fragment

@@ -763,6 +763,41 @@ void sigma_reserve(Context& c, int k, int precision) {
     grow_workspace(c, k);
 }
 
+size_t sigma_reserve_bytes(const Context& c, int k, int precision) {
+  // mirrors grow_assembly, grow_workspace and grow_workspace32: a buffer that grows is
+  // freed and allocated again, so each adds its new size less its old one; the strip
+  // buffers (independent of k) are allocated by the first growth only
+  if (c.order < 1 || k < 1) return 0;
+  auto r = [](size_t n, size_t e) { return ((n * e + 255) / 256) * 256; };
+  const size_t D = sizeof(double), F = sizeof(float);
+  const size_t o = c.o, v = c.v, X = c.naux, N = c.N, N8 = c.N8, ns = c.ns;
+  auto grow = [&](int cap, auto per_k) -> size_t {
+    if (k <= cap) return 0;
+    return per_k((size_t)k) - (cap > 0 ? per_k((size_t)cap) : 0);
+  };
+  size_t t = grow(c.kcap_asm, [&](size_t q) { return r(q * N, D) + r(4 * q * N, D); });
+  if (precision == 1) {
+    const bool stored = amplitudes_stored(c, 1);
+    const size_t ib = stored ? o : (size_t)c.strip_rows;
+    t += grow(c.kcap32, [&](size_t q) {
+      size_t b = 4 * r(q * N, F) + r(4 * q * N, F) + r(X * q, F) + r(q * X * N8, F) + r(q * o * ns * X * o, F);
+      if (c.order >= 2) b += r(ib * v * q * X, F);
+      return b;
+    });
+    if (c.kcap32 == 0 && c.order >= 2 && !stored)
+      t += r((size_t)c.strip_rows * v * N, F) + r((size_t)c.strip_rows * v * N8, F);
+  } else {
+    const size_t ib = c.tau ? o : (size_t)c.strip_rows;
+    t += grow(c.kcap, [&](size_t q) {
+      size_t b = r(X * q, D) + r(q * X * N, D) + r(q * o * ns * X * o, D);
+      if (c.order >= 2) b += r(ib * v * q * X, D);
+      return b;
+    });
+    if (c.kcap == 0 && c.order >= 2 && !c.tau) t += 2 * r((size_t)c.strip_rows * v * N, D);
+  }
+  return t;
+}
+
 namespace {
 
 void emit_products(Context& c, int order, int k, int prec, const double* V, double* AV, double* BV, double* SV,

@@ -22,6 +22,7 @@ struct SolveOptions {
   int contour_nodes = 6;  // Riesz: nodes on the upper half circle
   double contour_tol = 1e-4;  // Riesz: first-cycle solve tolerance (later: adaptive)
   int contour_maxit = 500;
+  int pass_vectors = 0;   // most vectors per product pass (0: as the device budget allows)
 };
 
 // One window solve's request for A, B and S products of k orthonormal vectors V

@@ -419,8 +419,8 @@ GemmDesc gd(int M, int N, int K, int tA, long lda, int tB, long ldb, long ldc) {
 class ProductBatcher : public ProductSink {
  public:
   using Req = ProductRequest;
-  ProductBatcher(Context& c, int active, int precision, std::mutex* enqueue)
-      : c_(c), active_(active), prec_(precision), enqueue_(enqueue) {}
+  ProductBatcher(Context& c, int active, int precision, std::mutex* enqueue, int max_pass = 0)
+      : c_(c), active_(active), prec_(precision), enqueue_(enqueue), max_pass_(max_pass) {}
   ~ProductBatcher() override {
     for (void* q : bufs_) c_.arena.free(q);
   }
@@ -432,9 +432,24 @@ class ProductBatcher : public ProductSink {
     SV_ = c_.arena.alloc<double>(n, "batch SV");
     bufs_ = {V_, AV_, BV_, SV_};
     cap_ = ktot;
-    sigma_reserve(c_, ktot, 0);
-    if (prec_ == 1) sigma_reserve(c_, ktot, 1);
+    // vectors per product pass: all of them when their product workspaces fit the
+    // device budget, else the largest count that fits (a batch then runs as several
+    // passes; with amplitudes rebuilt in strips each pass rebuilds them)
+    size_t avail;
+    if (c_.arena.budget()) {
+      avail = c_.arena.budget() > c_.arena.used() ? c_.arena.budget() - c_.arena.used() : 0;
+    } else {
+      size_t freeb = 0, total = 0;
+      PPW_HIP(hipMemGetInfo(&freeb, &total));
+      avail = (size_t)(0.9 * (double)freeb);
+    }
+    auto need = [&](int q) { return sigma_reserve_bytes(c_, q, 0) + (prec_ == 1 ? sigma_reserve_bytes(c_, q, 1) : 0); };
+    chunk_ = max_pass_ > 0 ? std::min(ktot, max_pass_) : ktot;
+    while (chunk_ > 1 && need(chunk_) > avail) --chunk_;
+    sigma_reserve(c_, chunk_, 0);
+    if (prec_ == 1) sigma_reserve(c_, chunk_, 1);
   }
+  int chunk() const { return chunk_; }
   void multiply(Req& r) override {
     std::unique_lock<std::mutex> lk(mu_);
     r.served = false;
@@ -472,10 +487,17 @@ class ProductBatcher : public ProductSink {
           PPW_HIP(hipMemcpyAsync(V_ + off * N, r->V, sizeof(double) * r->k * N, hipMemcpyDeviceToDevice, s));
           off += r->k;
         }
-        if (prec == 1)
-          sigma_core_f32(c_, c_.order, kt, V_, AV_, BV_, SV_);
-        else
-          sigma_core(c_, c_.order, kt, V_, AV_, BV_, SV_);
+        // passes of equal size (each at most chunk_ vectors)
+        const int npass = (kt + chunk_ - 1) / chunk_;
+        const int per = (kt + npass - 1) / npass;
+        for (int c0 = 0; c0 < kt; c0 += per) {
+          const int kc = std::min(per, kt - c0);
+          const size_t o0 = (size_t)c0 * N;
+          if (prec == 1)
+            sigma_core_f32(c_, c_.order, kc, V_ + o0, AV_ + o0, BV_ + o0, SV_ + o0);
+          else
+            sigma_core(c_, c_.order, kc, V_ + o0, AV_ + o0, BV_ + o0, SV_ + o0);
+        }
         off = 0;
         for (auto* r : pending_) {
           if (r->prec != prec) continue;
@@ -507,6 +529,8 @@ class ProductBatcher : public ProductSink {
   double *V_ = nullptr, *AV_ = nullptr, *BV_ = nullptr, *SV_ = nullptr;
   std::vector<void*> bufs_;
   int cap_ = 0;
+  int chunk_ = 0;
+  int max_pass_ = 0;
 };
 
 // Block size, basis limit and vectors per extension of one window solve (as the
@@ -850,21 +874,6 @@ class Solver {
   }
   void coeff_dots(int k, const double* X1, const double* Y1, const double* X2, const double* Y2, double* out) {
     coeff_dots_kernel<<<(k + 63) / 64, 64, 0, s_>>>(nb_, k, kmax_, X1, Y1, X2, Y2, out);
-  }
-
-  // FP64 products of the whole current basis (mixed precision: the subspace built with
-  // FP32 products is kept, only its products are recomputed exactly)
-  void remultiply_basis() {
-    for (int c0 = 0; c0 < nb_; c0 += kmax_) {
-      const int kc = std::min(kmax_, nb_ - c0);
-      const size_t off = (size_t)c0 * N_;
-      products(kc, Q_ + off, true);
-      axpby((long)kc * N_, 1.0, AV_, 0.0, P0_ + off, s_);
-      axpby((long)kc * N_, 1.0, BV_, 1.0, P0_ + off, s_);
-      axpby((long)kc * N_, 1.0, AV_, 0.0, P1_ + off, s_);
-      axpby((long)kc * N_, -1.0, BV_, 1.0, P1_ + off, s_);
-      PPW_HIP(hipMemcpyAsync(PS_ + off, SV_, sizeof(double) * kc * N_, hipMemcpyDeviceToDevice, s_));
-    }
   }
 
   // thick restart: new basis = orthonormal span of the X+Y and X-Y halves of the block's Ritz vectors
@@ -1245,10 +1254,10 @@ void Solver::run(double* energies, double* vectors, double* osc, pp_solve_info* 
       std::fprintf(stderr, "[ppwin] window %d omega0 %.4f cycle %d basis %d products %ld worst %.3e refined %d\n", id_,
                    w0_, cycle, nb_, products_, worst, refined ? 1 : 0);
     if (mixed) {
-      // FP32 products build the subspace until the window is resolved to the FP32
-      // level (or stops improving); then the basis gets FP64 products once and the
-      // solve continues as in FP64 (every later product FP64, restart blocks FP64);
-      // the returned vectors are accepted on residuals of FP64 products only.
+      // Reduced-precision products build the subspace until the window is resolved to
+      // that level (or stops improving); then a thick restart onto the block with FP64
+      // products, and the solve continues as in FP64 (every later product FP64); the
+      // returned vectors are accepted on residuals of FP64 products only.
       if (!refined && (all || worst <= switch_tol || stalled)) {
         // thick restart onto the block (inner pairs first): only its X+Y and X-Y halves
         // get FP64 products, and every later product is FP64
@@ -1368,7 +1377,7 @@ void window_solve_many(Context& c, const SolveOptions& opt, int nw, const double
   for (int g = 0; g < ngroups; ++g) {
     int members = 0;
     for (int w = g; w < nw; w += ngroups) ++members;
-    pbs.emplace_back(new ProductBatcher(c, members, opt.precision, &enqueue));
+    pbs.emplace_back(new ProductBatcher(c, members, opt.precision, &enqueue, opt.pass_vectors));
   }
   std::vector<std::unique_ptr<Solver>> sv;
   std::vector<int> ktot(ngroups, 0);

@@ -44,7 +44,8 @@ def summarize(path, limit=25):
         for name, n, tot, avg, pct in rows[:limit]:
             out.append(f"| `{short(name)}` | {n} | {tot / 1e9:.2f} | {avg / 1e6:.3f} | {pct:.1f} |")
         return "\n".join(out)
-    c = sqlite3.connect(path)
+    # read-only: a path that does not exist is an error, never a new empty database
+    c = sqlite3.connect(f"file:{path}?mode=ro", uri=True)
     rows = list(c.execute("select name, total_calls, total_duration, average, percentage from top_kernels"))
     for name, n, tot, avg, pct in rows[:limit]:
         out.append(f"| `{short(name)}` | {n} | {tot / 1e6:.2f} | {avg / 1e3:.2f} | {pct:.1f} |")
@@ -143,6 +144,10 @@ def mfma(path, limit=14):
 
 
 if __name__ == "__main__":
+    if len(sys.argv) < 2 or sys.argv[1] in ("-h", "--help") or (
+            sys.argv[1].startswith("-") and sys.argv[1] not in ("--counters", "--bandwidth", "--mfma", "--grid")):
+        print(__doc__)
+        sys.exit(0 if len(sys.argv) >= 2 and sys.argv[1] in ("-h", "--help") else 2)
     if sys.argv[1] == "--counters":
         print(counters(sys.argv[2:]))
     elif sys.argv[1] == "--bandwidth":

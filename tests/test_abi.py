@@ -47,6 +47,8 @@ def test_host_only_helpers(lib):
     opt = b.pp_options()
     lib.pp_default_options(ctypes.byref(opt))
     assert opt.precision == 0 and opt.tol == 1e-9 and opt.max_cycles > 0
+    # last field of the struct: the binding's layout matches the header's
+    assert opt.contour_maxit == 500 and opt.pass_vectors == 0
     lib.pp_status_string.restype = ctypes.c_char_p
     for code in range(7):
         assert lib.pp_status_string(code)

@@ -246,6 +246,20 @@ def test_window_mixed_precision(P, omega0, nr, prec):
     assert np.all(info["residual"] <= 1e-9)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "sbf16"])
+def test_window_passes_capped(P, prec):
+    """Product passes capped at 7 vectors (pass_vectors), amplitudes rebuilt in strips of
+    5 occupied rows: each window's 20-vector requests run as passes of equal size, every
+    pass rebuilding the strips; two batched windows still match the oracle."""
+    sys = gen(7, 12, 40, 100)
+    pp = {"fp64": P.PP_FP64, "sbf16": P.PP_SPLIT_BF16}[prec]
+    print(f"[window] passes capped at 7 vectors, {prec}", flush=True)
+    with P.Handle.from_system(sys, order=2, store_amplitudes=0, strip_rows=5, pass_vectors=7, precision=pp) as h:
+        e, vec, f, infos = h.window_solve_batch([0.45, 1.1], 8)
+    for w, (omega0, nr) in enumerate(((0.45, 8), (1.1, 8))):
+        _check_window(sys, 2, omega0, nr, e[w], vec[w], f[w], infos[w])
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "sbf16"])
 def test_window_survey_completeness(P, precision):
     """The full 40/160/600 workload in the launch configuration the benchmark times
