@@ -130,7 +130,7 @@ Context* setup_context(const SetupParams& p) {
     c->order = p.order;
     c->split_bf16 = p.split_bf16 && p.want_f32;
     c->N = (long)p.o * p.v;
-    c->N8 = (c->N + 7) / 8 * 8;
+    c->N8 = padded_stride(c->N);
     c->X8 = (p.naux + 7) / 8 * 8;
     c->device = p.device;
     PPW_HIP(hipSetDevice(p.device));
@@ -708,7 +708,7 @@ Footprint context_footprint(int o, int v, int X, int order, bool dip, bool store
   auto r = [](size_t bytes) { return ((bytes + 255) / 256) * 256; };
   const size_t D = sizeof(double), F = sizeof(float);
   const size_t N = (size_t)o * v, K = (size_t)k;
-  const size_t N8 = (N + 7) / 8 * 8, X8 = ((size_t)X + 7) / 8 * 8;
+  const size_t N8 = (size_t)padded_stride((long)N), X8 = ((size_t)X + 7) / 8 * 8;
   const size_t ns = order >= 2 ? 2 : 1;
   const int ib = order >= 2 ? std::max(1, std::min(strip_rows > 0 ? strip_rows : o, o)) : 0;
   size_t keep = r(o * D) + r(v * D) + r(X * (size_t)o * o * D) + r(X * (size_t)v * v * D) + r(ns * X * N * D);
@@ -949,12 +949,18 @@ int sigma_group(const std::vector<PassJob>& jobs, hipStream_t s) {
     for (auto& t : tapes) {
       if (p >= t.size()) continue;
       Step& st = t[p];
-      if (st.kind == 0)
+      // a GEMM whose reduction splits the launch would choose by itself is issued without
+      // split-K, grouped or not, so that each system's products round the same way
+      // whichever systems share the pass (fixed splits are kept)
+      if (st.kind == 0) {
         g64.push_back(st.g64);
-      else if (st.kind == 1)
+        if (g64.back().d.splitk == 0) g64.back().d.splitk = 1;
+      } else if (st.kind == 1) {
         g32.push_back(st.g32);
-      else
+        if (g32.back().d.splitk == 0) g32.back().d.splitk = 1;
+      } else {
         st.fn(s);
+      }
     }
     if (!g64.empty()) grouped += gemm_group_f64(g64, s);
     if (!g32.empty()) grouped += gemm_group_f32(g32, s);

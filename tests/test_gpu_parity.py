@@ -29,6 +29,8 @@ SYSTEMS = {
     "c1": dict(seed=1, o=8, v=24, naux=64),
     "mid": dict(seed=7, o=12, v=40, naux=100, b_scale=0.3),
     "ragged": dict(seed=11, o=5, v=19, naux=23, b_scale=0.5),
+    # N = 1024: FP32 rows of N values would start 4 KiB apart, so their stride is padded
+    "pad": dict(seed=13, o=16, v=64, naux=40, b_scale=0.3),
 }
 
 
@@ -207,14 +209,15 @@ def test_fp32_products_within_single_precision(P):
         assert err <= 2e-6 * np.abs(corr).max() + 1e-14, (j, err, np.abs(corr).max())
 
 
-@pytest.mark.parametrize("name", ["mid", "ragged"])
+@pytest.mark.parametrize("name", ["mid", "ragged", "pad"])
 @pytest.mark.parametrize("store", [1, 0])
 def test_split_bf16_products(P, name, store):
     """Split-BF16 amplitude contraction (FP32 elsewhere, FP64 diagonal and assembly): the
     products agree with the oracle to the split's accuracy, a relative 2^-16 per product,
     on the parts beyond the diagonal; amplitudes stored or rebuilt in strips (then their
     integrals are split-BF16 products too), on a system whose particle-hole dimension and
-    auxiliary size are whole 8-value chunks and on one where neither is."""
+    auxiliary size are whole 8-value chunks, on one where neither is, and on one whose
+    rows are padded past a 4 KiB multiple."""
     torch = pytest.importorskip("torch")
     sys = _sys(name)
     print(f"[sbf16 products] system={name} store={store} N={sys.N} naux={sys.naux}", flush=True)

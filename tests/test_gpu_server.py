@@ -197,3 +197,28 @@ def test_server_o40_request_alone_and_in_mix(P, prec):
     for (s, w, nr), q in zip(mix[:2] + mix[2:], rs):
         e1, f1 = _oracle(s, w, nr)
         _check_vs(q["energies"], q["osc"], e1, f1)
+
+
+def test_server_results_do_not_depend_on_the_mix(P):
+    """A request's products do not depend on which requests share its passes: the o = 40
+    request served alone and then beside an o = 24 request (large enough that their GEMMs
+    go out as grouped launches) and a small one gives bitwise equal roots, strengths and
+    vectors (no GEMM of a merged pass takes split-K, grouped or launched alone)."""
+    g = _request_golden()
+    big = gen(g["seed"], g["o"], g["v"], g["naux"])
+    mid = gen(4041, 24, 96, 288)
+    print("[server mix] alone", flush=True)
+    with P.Server(max_active=8) as srv:
+        alone = srv.wait(srv.submit_system(big, g["omega0"], g["n_roots"]))
+    print("[server mix] in a mix", flush=True)
+    with P.Server(max_active=8) as srv:
+        ids = [srv.submit_system(mid, 0.7, 6), srv.submit_system(big, g["omega0"], g["n_roots"]),
+               srv.submit_system(*_systems()[0])]
+        res = [srv.wait(i) for i in ids]
+        st = srv.stats()
+    assert st["peak_running"] >= 2 and st["grouped_launches"] > 0, st
+    mixed = res[1]
+    assert np.array_equal(alone["energies"], mixed["energies"])
+    assert np.array_equal(alone["osc"], mixed["osc"])
+    assert np.array_equal(alone["vectors"], mixed["vectors"])
+    _check_vs(mixed["energies"], mixed["osc"], np.array(g["energies"]), np.array(g["osc"]))
