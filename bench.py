@@ -76,7 +76,9 @@ def hhat_traffic(flops_per_launch, precision):
 # KiB per dispatch) scaled by what the same counters read for a plain 1 GiB device copy
 # in the same runs (--copy-calibration); valid for the GEMM source with this digest and
 # launches of this size only (else null).
-PRODUCT_TRAFFIC = None
+PRODUCT_TRAFFIC = {"gemm_sha256_16": "10c6f2ce9ca92a7d", "flops_per_launch": 281474976710656.0,
+                   "fetch_kib": 402842875.0, "write_kib": 2392064.0,
+                   "copy_fetch_kib": 524303.6, "copy_write_kib": 1048576.0}
 
 
 def product_traffic(flops_per_launch):
