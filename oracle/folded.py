@@ -1,9 +1,19 @@
-"""The paper's interior solver on the CPU, with dense matrix-vector products.
+"""The interior solver on the CPU, with dense matrix-vector products.
 
 Test infrastructure (see the package docstring): never used by the product.
 
-Steps (interior-eigenvalue subsection of the Theory section), with the readings
-the paper leaves open:
+What comes from the paper (interior-eigenvalue subsection of the Theory section)
+and what does not.  The folded target, the inverse-Krylov extension by weighted
+Jacobi sweeps and the weight alpha from the folded Rayleigh quotient are the
+paper's method, with the readings below where it is silent.  The paired
+(X+Y, X-Y) subspace, the 2x2 diagonal corrections from the residuals, the
+restarts and the completeness rule are additions of this implementation, shared
+with the device solver (they were developed together).  A test that this module
+finds the same roots as the full diagonalisation therefore checks that design
+against the exact pencil, not an independent rendering of the paper's
+algorithm; the device solver is compared with the exact pencil (pencil.py) only.
+
+Steps, with the readings the paper leaves open:
 
 * Target.  The pencil M z = omega Sigma z near a chosen omega0, with
   Z = M - omega0 Sigma (symmetric) and the folded Rayleigh quotient
