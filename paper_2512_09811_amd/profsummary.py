@@ -104,8 +104,16 @@ def bandwidth(fetch, write, trace, limit=40):
     dur = defaultdict(list)
     for r in csv.DictReader(open(trace)):
         dur[short(r["Kernel_Name"])].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9)
-    cf = 1048576.0 / max(per[("__amd_rocclr_copyBuffer", "FETCH_SIZE")])
-    cw = 1048576.0 / max(per[("__amd_rocclr_copyBuffer", "WRITE_SIZE")])
+    # the calibration copies are the 1 GiB device copies: the copy dispatches that write
+    # exactly 1 GiB, and the dispatches at the same positions of the (deterministic)
+    # fetch run
+    cfv = per[("__amd_rocclr_copyBuffer", "FETCH_SIZE")]
+    cwv = per[("__amd_rocclr_copyBuffer", "WRITE_SIZE")]
+    idx = [i for i, x in enumerate(cwv) if x == 1048576.0 and i < len(cfv)]
+    if not idx:
+        raise SystemExit("no 1 GiB calibration copy in the counter runs (bench.py --copy-calibration)")
+    cf = 1048576.0 / (sum(cfv[i] for i in idx) / len(idx))
+    cw = 1.0
     rows = []
     for k in dur:
         f, w = per.get((k, "FETCH_SIZE")), per.get((k, "WRITE_SIZE"))
