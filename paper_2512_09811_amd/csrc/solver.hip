@@ -217,43 +217,6 @@ __global__ void residual_norms_kernel(long N, int nr, const double* __restrict__
   }
 }
 
-// Residuals of Ritz pairs from products of their halves: rows [u_0..u_nt-1, w_0..w_nt-1]
-// of V, AV, BV, SV.  out[j] = |ru|^2 + |rw|^2, out[nt + j] = |u|^2 + |w|^2 (= 2 |y|^2 and
-// |ru|^2 + |rw|^2 = 2 |r|^2, so |r|/|y| = sqrt(out[j] / out[nt + j])).
-__global__ void exact_residual_kernel(long N, int nt, const double* __restrict__ th, const double* __restrict__ V,
-                                      const double* __restrict__ AV, const double* __restrict__ BV,
-                                      const double* __restrict__ SV, double* __restrict__ out) {
-  __shared__ double red[2][kB / 64];
-  const int j = blockIdx.x;
-  const long bu = (long)j * N, bw = (long)(nt + j) * N;
-  const double t = th[j];
-  double a = 0.0, b = 0.0;
-  for (long i = threadIdx.x; i < N; i += blockDim.x) {
-    const double ru = AV[bu + i] + BV[bu + i] - t * SV[bw + i];
-    const double rw = AV[bw + i] - BV[bw + i] - t * SV[bu + i];
-    a += ru * ru + rw * rw;
-    b += V[bu + i] * V[bu + i] + V[bw + i] * V[bw + i];
-  }
-  for (int off = 32; off > 0; off >>= 1) {
-    a += __shfl_down(a, off, 64);
-    b += __shfl_down(b, off, 64);
-  }
-  if ((threadIdx.x & 63) == 0) {
-    red[0][threadIdx.x >> 6] = a;
-    red[1][threadIdx.x >> 6] = b;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double sa = 0, sb = 0;
-    for (int w = 0; w < kB / 64; ++w) {
-      sa += red[0][w];
-      sb += red[1][w];
-    }
-    out[j] = sa;
-    out[nt + j] = sb;
-  }
-}
-
 // corrections for the listed roots: solve [[ap, -th s], [-th s, am]] [cu; cw] = -[ru; rw]
 __global__ void correction_kernel(long N, int na, const int* __restrict__ idx_list, const double* __restrict__ th,
                                   double clampv, const double* __restrict__ dA, const double* __restrict__ dB,
@@ -497,6 +460,11 @@ class ProductBatcher : public ProductSink {
             sigma_core_f32(c_, c_.order, kc, V_ + o0, AV_ + o0, BV_ + o0, SV_ + o0);
           else
             sigma_core(c_, c_.order, kc, V_ + o0, AV_ + o0, BV_ + o0, SV_ + o0);
+          if (trace_) {
+            // progress of long passes (the wait serializes the passes; tracing only)
+            PPW_HIP(hipStreamSynchronize(s));
+            std::fprintf(stderr, "[ppwin] product pass of %d vectors (%s) done\n", kc, prec ? "reduced" : "FP64");
+          }
         }
         off = 0;
         for (auto* r : pending_) {
@@ -531,6 +499,7 @@ class ProductBatcher : public ProductSink {
   int cap_ = 0;
   int chunk_ = 0;
   int max_pass_ = 0;
+  bool trace_ = std::getenv("PPWIN_TRACE") != nullptr;
 };
 
 // Block size, basis limit and vectors per extension of one window solve (as the
@@ -919,27 +888,6 @@ class Solver {
     nb_ = nk;
   }
 
-  // FP64 residual norms |(M - theta Sigma) y| / |y| of the listed Ritz pairs, from
-  // FP64 products of their X+Y and X-Y halves.
-  std::vector<double> exact_residuals(const std::vector<int>& tg, const std::vector<double>& th) {
-    const int nt = (int)tg.size();
-    const int n = nb_;
-    upload(sel_, tg);
-    gather_cols_kernel<<<gridn((long)n * nt), kB, 0, s_>>>(n, nt, sel_, us_, rld_, c1_, nt, 0);
-    gather_cols_kernel<<<gridn((long)n * nt), kB, 0, s_>>>(n, nt, sel_, ws_, rld_, c2_, nt, 0);
-    expand(nt, n, c1_, nt, Q_, V_);
-    expand(nt, n, c2_, nt, Q_, V_ + (size_t)nt * N_);
-    products(2 * nt, V_, true);
-    std::vector<double> ths(nt);
-    for (int q = 0; q < nt; ++q) ths[q] = th[tg[q]];
-    upload(th2_, ths);
-    exact_residual_kernel<<<nt, kB, 0, s_>>>(N_, nt, th2_, V_, AV_, BV_, SV_, stats_);
-    auto st = fetch(stats_, 2 * (size_t)nt);
-    std::vector<double> out(nt);
-    for (int q = 0; q < nt; ++q) out[q] = std::sqrt(st[q] / st[nt + q]);
-    return out;
-  }
-
   // Riesz projector mode: V_ (X rows [0, k), Y rows [k, 2k)) <- P V_ on the circle of
   // radius rad_ around omega0
   void contour_step(int k) {
@@ -1270,27 +1218,11 @@ void Solver::run(double* energies, double* vectors, double* osc, pp_solve_info* 
         continue;
       }
       if (refined && all) {
-        auto rex = exact_residuals(out, R.th);
-        if (trace_) {
-          double mx = 0.0;
-          for (double x : rex) mx = std::max(mx, x);
-          std::fprintf(stderr, "[ppwin] window %d FP64 residual check: worst %.3e\n", id_, mx);
-        }
-        bool ok = true;
-        for (size_t q = 0; q < out.size(); ++q) {
-          R.rn[out[q]] = rex[q];
-          ok = ok && rex[q] <= opt_.tol;
-        }
-        if (ok) {
-          converged = true;
-          ++cycle;
-          break;
-        }
-        restart(blk);
-        knew = 0;
-        best_worst = 1e300;
-        since_best = 0;
-        continue;
+        // every basis product since the switch is FP64, so these Rayleigh-Ritz residuals
+        // are residuals of FP64 products
+        converged = true;
+        ++cycle;
+        break;
       }
     } else if (all) {
       converged = true;
