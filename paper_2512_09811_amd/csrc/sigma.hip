@@ -513,6 +513,7 @@ void contract(Context& c, const Ops<T>& t, Emit<T>& e, int order, int k, const T
   const int o = c.o, v = c.v, X = c.naux;
   const long N = c.N;
   const T one = T(1), zero = T(0), mone = T(-1);
+  constexpr bool fp32 = sizeof(T) == sizeof(float);
   if (rg.pre) {
   // J: c[P][q] = sum_ia Bov[P][ia] V[q][ia];  J[q][ia] = sum_P c[P][q] Bov[P][ia]
   e.gemm(gd(X, k, (int)N, 0, N, 1, N, k), one, t.Bov, V, zero, t.c, c.ws);
@@ -555,13 +556,13 @@ void contract(Context& c, const Ops<T>& t, Emit<T>& e, int order, int k, const T
       e.gemm(d, one, V, t.BovLam, zero, t.U, c.ws);
     }
     if (ns == c.ns) {
-      // one GEMM over rows (q,i), with the reduction splits the same product batched
-      // over q would take (identical sums and rounding)
+      // one GEMM over rows (q,i); in FP64 with the reduction splits the same product
+      // batched over q would take (identical sums and rounding), in FP32 its own
       GemmDesc bq = gd(o, v, o * ns * X, 1, o, 0, v, v);
       bq.nb1 = k;
       GemmDesc d = gd(k * o, v, o * ns * X, 1, (long)k * o, 0, v, v);
       d.tile = 64;
-      d.splitk = gemm_auto_splitk(bq, c.ws.bytes, sizeof(T) == sizeof(float));
+      d.splitk = gemm_auto_splitk(fp32 ? d : bq, c.ws.bytes, fp32);
       e.gemm(d, mone, t.U, t.R, zero, BV, c.ws);
     } else {
       // first-order product on a second-order handle: K_B(V) = sum_(j,P) U[j][P][q][i] Bov[P][j][a],
@@ -615,8 +616,10 @@ void contract(Context& c, const Ops<T>& t, Emit<T>& e, int order, int k, const T
   auto outputs = [&](const T* H, int i0, int ib) {
     const long hq = (long)ib * v * X;
     // BV[q][i][a] += sum_(c,P) H[q][(i,c)][P] Bvv[P][c][a]: one GEMM with rows (q,i),
-    // written at q N + (i0 + i) v.  Its reduction splits are those the same product
-    // batched over q would take, so every element is summed and rounded alike.
+    // written at q N + (i0 + i) v.  In FP64 its reduction splits are those the same
+    // product batched over q would take, so every element is summed and rounded alike; in
+    // FP32 it takes its own (with few rows, k ib = 128 at 256/1024/4096, the batched
+    // form's split would leave the GEMM on 32 workgroups).
     {
       GemmDesc bq = gd(ib, v, X, 0, (long)v * X, 0, (long)v * v, v);
       bq.KB = v;
@@ -630,7 +633,7 @@ void contract(Context& c, const Ops<T>& t, Emit<T>& e, int order, int k, const T
       d.cRm = ib;
       d.cSm = N;
       d.tile = 64;
-      d.splitk = gemm_auto_splitk(bq, c.ws.bytes, sizeof(T) == sizeof(float));
+      d.splitk = gemm_auto_splitk(fp32 ? d : bq, c.ws.bytes, fp32);
       e.gemm(d, one, H, t.Bvv, one, BV + (size_t)i0 * v, c.ws);
     }
     // BV[q][i][a] -= sum_(kk,P) Boo[P][i][kk] H[q][(kk,a)][P]   kk in i0..i0+ib-1
