@@ -1229,9 +1229,18 @@ void Solver::run(double* energies, double* vectors, double* osc, pp_solve_info* 
       ++cycle;
       break;
     }
+    // corrections for the block's unconverged pairs; after the precision switch of a
+    // mixed solve only for the targets and inner pairs (the Ritz vectors already hold
+    // the reduced-precision solution, and the guard pairs' FP64 products cost more than
+    // they speed up the targets)
     std::vector<int> act;
-    for (int j : blk)
-      if (R.rn[j] > opt_.tol) act.push_back(j);
+    for (int j : blk) {
+      if (R.rn[j] <= opt_.tol) continue;
+      if (mixed && refined && !cf_ && std::find(inner.begin(), inner.end(), j) == inner.end() &&
+          std::find(tgt.begin(), tgt.end(), j) == tgt.end())
+        continue;
+      act.push_back(j);
+    }
     if (act.empty()) act = blk;
     knew = (int)act.size();
     upload(sel_, act);
