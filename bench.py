@@ -302,8 +302,9 @@ def large_main(args):
 def serve_main(args):
     """Serving stream: requests drawn like the serving workload (n_vir = 4 n_occ,
     n_aux = 12 n_occ, omega0 ~ U[0.3, 1.5], 4-12 roots), submitted to one pp_server.
-    After a short warm-up (runtime start), the timed requests are first submitted all at
-    once to a fresh server: their completion rate is the saturated throughput X.  The same
+    Every request is solved to the window benchmark's tolerance (--tol).  After a short
+    warm-up (runtime start), the timed requests are first submitted all at once to a fresh
+    server: their completion rate is the saturated throughput X.  The same
     requests then arrive as a Poisson process at 0.8 X (the timed stream: value, latency
     from submission to result).  Last, the plain path: one FP64 handle per request, one
     request at a time."""
@@ -318,14 +319,14 @@ def serve_main(args):
     reqs = [gen_request(r, lo, hi) for r in range(nwarm + args.requests)]
     print(f"[serve] generated {len(reqs)} requests in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     timed = reqs[nwarm:]
-    with P.Server(precision=prec) as srv:
+    with P.Server(precision=prec, tol=args.tol) as srv:
         ids = [srv.submit_system(s_, w, nr) for s_, w, nr in reqs[:nwarm]]
         for i in ids:
             srv.wait(i, allow_unconverged=True)
     print("[serve] warm-up done", file=sys.stderr, flush=True)
     # saturated: every timed request at once
     t1 = time.perf_counter()
-    with P.Server(precision=prec) as srv2:
+    with P.Server(precision=prec, tol=args.tol) as srv2:
         ids2 = [srv2.submit_system(s_, w, nr) for s_, w, nr in timed]
         for j, i in enumerate(ids2):
             srv2.wait(i, allow_unconverged=True)
@@ -336,7 +337,7 @@ def serve_main(args):
     lam = 0.8 * x_sat
     print(f"[serve] saturated {x_sat:.2f} solves/s ({st2['mean_requests_per_pass']:.2f} requests per pass); "
           f"arrivals at {lam:.2f}/s", file=sys.stderr, flush=True)
-    srv = P.Server(precision=prec)
+    srv = P.Server(precision=prec, tol=args.tol)
     rng = np.random.default_rng(12345)
     gaps = rng.exponential(1.0 / lam, args.requests)
     ids = [None] * len(timed)
@@ -367,7 +368,7 @@ def serve_main(args):
     if not args.no_plain_compare:
         t1 = time.perf_counter()
         for j, (s_, w, nr) in enumerate(timed):
-            with P.Handle.from_system(s_, order=2) as h:
+            with P.Handle.from_system(s_, order=2, tol=args.tol) as h:
                 h.window_solve(w, nr, allow_unconverged=True)
             if (j + 1) % 8 == 0:
                 print(f"[serve] plain path {j + 1}/{len(timed)}", file=sys.stderr, flush=True)
@@ -389,7 +390,7 @@ def serve_main(args):
         "data": "synthetic (seeded serving stream)",
         "config": {"workload": f"serving stream: {args.requests} requests, n_occ ~ U{{{lo}..{hi}}}, n_vir = 4 n_occ, "
                                f"n_aux = 12 n_occ, omega0 ~ U[0.3,1.5], 4-12 roots, second order",
-                   "arrival_rate_per_s": lam, "mean_n_occ": float(np.mean(occ))},
+                   "arrival_rate_per_s": lam, "mean_n_occ": float(np.mean(occ)), "solver_tol": args.tol},
         "windows_converged": f"{conv}/{len(res)}",
         "latency_p50_s": float(np.percentile(lat, 50)),
         "latency_p99_s": float(np.percentile(lat, 99)),
