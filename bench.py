@@ -18,8 +18,9 @@ is compared with the FP64 pass on the same vectors.
 value = sigma-build TFLOP/s (algorithmic flops of the parts timed / wall time).  The
 40/160/600 window solves (solves/s at 1e-6 Ha against the oracle, FP64 and split-BF16,
 p50/p99 latency) are reported as extra fields.  ``--workload mp2_o40_v160_x600`` gives
-that window benchmark as its own line; ``--serve`` the serving stream; ``--riesz`` the
-Riesz-projector comparison.
+that window benchmark as its own line; ``--large mp2_o200_v800_x3000`` a window of a
+device-drawn large system in split BF16 and FP64 with the roots cross-checked; ``--serve``
+the serving stream; ``--riesz`` the Riesz-projector comparison.
 
 Prints ONE JSON line (rank 0): roofline of the dominant kernel (the amplitude
 contraction, split-BF16, priced against the BF16 peak / 3) and the CPU oracle baseline.
